@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the lattice Boltzmann method itself: only
+the pipe configurations (plain numbers) and a counter-based random generator
+for the trigger-force amplitudes.  Both the HIP library and the FP64 oracle
+receive the same amplitude arrays from here.
+
+Parameter sources (arXiv:2405.12082, Section II.B): nu = 0.0032,
+u* = 0.00388, Re_tau = u* R / nu ~ 181.3, Re ~ 5329.3 (bulk velocity and
+diameter), u* = sqrt(h R / 2), forcing period T ~ 0.052 T^LET with
+T^LET = R / u*, k_z = 3, kappa = 0.5, l_0 = 0.2 R, l = 0.4 R.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# --- the paper's printed flow parameters (Section II.B) ---
+PAPER_NU = 0.0032
+PAPER_U_TAU = 0.00388
+PAPER_RE_TAU = 181.3
+PAPER_RE_BULK = 5329.3
+PAPER_RADIUS = 149.5
+PAPER_GRID = (300, 300, 600)
+#: bulk-to-friction velocity ratio implied by the printed Reynolds numbers:
+#: Re = U_b (2R) / nu and Re_tau = u* R / nu give U_b / u* = Re / (2 Re_tau).
+BULK_OVER_UTAU = PAPER_RE_BULK / (2.0 * PAPER_RE_TAU)
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(state: int):
+    """One step of SplitMix64 (Steele, Lea & Flood 2014). Returns (state, out)."""
+    state = (state + 0x9E3779B97F4A7C15) & _MASK64
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return state, z ^ (z >> 31)
+
+
+def uniform01(seed: int, n: int) -> np.ndarray:
+    """n doubles in [0, 1) from SplitMix64 seeded with ``seed`` (53-bit mantissa)."""
+    s = seed & _MASK64
+    out = np.empty(n)
+    for k in range(n):
+        s, z = splitmix64(s)
+        out[k] = (z >> 11) * (1.0 / (1 << 53))
+    return out
+
+
+def amplitude_unit(u_tau: float, period: float) -> float:
+    """Acceleration per unit dimensionless amplitude: u_b * pi / T.
+
+    A mode of peak acceleration A acting for half a period T/2 with a
+    sin(2 pi t/T) time factor imparts a velocity impulse A T / pi, so an
+    amplitude s in units of u_b pi / T imparts s * u_b.  The bulk velocity is
+    taken from the paper's Reynolds numbers, u_b = (Re / 2 Re_tau) u*."""
+    return BULK_OVER_UTAU * u_tau * math.pi / period
+
+
+def amplitudes(seed: int, n_modes: int, u_tau: float, period: float, s_max: float = 0.05):
+    """Trigger-force amplitudes for one pipe: 2*n_modes values, ordered
+    (m=1 cos, m=1 sin, m=2 cos, ...), each s * amplitude_unit with s ~ U(0, s_max)."""
+    s = uniform01(seed, 2 * n_modes) * s_max
+    return s * amplitude_unit(u_tau, period)
+
+
+def batch_amplitudes(seed0: int, batch: int, n_modes: int, u_tau: float, period: float):
+    """[batch][2*n_modes] amplitudes, pipe b seeded with seed0 + b."""
+    return np.stack([amplitudes(seed0 + b, n_modes, u_tau, period) for b in range(batch)]) \
+        if n_modes > 0 else np.zeros((batch, 0))
+
+
+def _pipe(nx, ny, nz, radius, nu, u_tau, *, batch=1, n_modes=6, force_off_step=None, steps=1000,
+          init=1, seed=0, **extra):
+    tau = 3.0 * nu + 0.5
+    h = 2.0 * u_tau * u_tau / radius
+    period = round(0.052 * radius / u_tau)
+    cfg = dict(nx=nx, ny=ny, nz=nz, batch=batch, radius=float(radius), tau=tau, accel_z=h,
+               n_modes=n_modes, kz=3.0, kappa=0.5, l0_frac=0.2, l_frac=0.4,
+               period=float(period), force_off_step=int(force_off_step if force_off_step is not None
+                                                         else steps),
+               storage=0, wall=0, pattern=0, init=init, u_tau=u_tau, steps=steps, seed=seed)
+    cfg.update(extra)
+    return cfg
+
+
+def preset(name: str) -> dict:
+    """Named pipe configurations (plain dicts; keys are config fields plus
+    ``steps`` and ``seed``)."""
+    if name == "laminar":  # 24x24x48, R=10, tau=0.8, a=1e-6, rest start, halfway bounce-back
+        return dict(nx=24, ny=24, nz=48, batch=1, radius=10.0, tau=0.8, accel_z=1e-6, n_modes=0,
+                    kz=3.0, kappa=0.5, l0_frac=0.2, l_frac=0.4, period=1.0, force_off_step=0,
+                    storage=0, wall=0, pattern=0, init=0, u_tau=0.0, steps=500, seed=0)
+    if name == "turbulent":  # 192x192x1152, R=90, Re_tau ~ 181 at the paper's u*
+        nu = PAPER_U_TAU * 90.0 / PAPER_RE_TAU
+        return _pipe(192, 192, 1152, 90.0, nu, PAPER_U_TAU, force_off_step=5000, steps=20000)
+    if name == "precision_ref":  # 64x64x256, R=30, the turbulent pipe's tau and u*
+        nu = PAPER_U_TAU * 90.0 / PAPER_RE_TAU
+        return _pipe(64, 64, 256, 30.0, nu, PAPER_U_TAU, force_off_step=2500, steps=5000)
+    if name == "batched":  # 64 pipes of 64x64x256, R=30, nu = 0.0032
+        return _pipe(64, 64, 256, 30.0, PAPER_NU, PAPER_U_TAU, batch=64, force_off_step=5000,
+                     steps=5000)
+    if name == "adjoint":  # 96x96x384, R=45, nu = 0.0032, J over steps 1501..2000
+        return _pipe(96, 96, 384, 45.0, PAPER_NU, PAPER_U_TAU, force_off_step=2000, steps=2000,
+                     obs_begin=1501, obs_end=2001, checkpoint_every=100)
+    raise KeyError(name)
+
+
+def preset_amplitudes(cfg: dict) -> np.ndarray:
+    """[batch][2*n_modes] amplitudes for a preset (seed, seed+1, ...)."""
+    return batch_amplitudes(int(cfg.get("seed", 0)), int(cfg.get("batch", 1)),
+                            int(cfg["n_modes"]), float(cfg["u_tau"]), float(cfg["period"]))
+
+
+def random_populations(seed: int, shape, scale: float = 1e-3) -> np.ndarray:
+    """Seeded random deviation field for parity tests: N(0, scale) values."""
+    return np.random.default_rng(seed).normal(0.0, scale, size=shape)
+
+
+def dims_of(cfg: dict):
+    return int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])

@@ -1,0 +1,25 @@
+"""Shared test setup: repository root on sys.path and the ``gpu`` marker."""
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+@pytest.fixture(scope="session")
+def oracle_mod():
+    from oracle import oracle as O
+    try:
+        O.lib()
+    except RuntimeError:
+        from oracle import build
+        build.build()
+        O.lib()
+    return O
