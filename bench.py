@@ -1,0 +1,181 @@
+"""Benchmark of the fused D3Q27 MRT stream-collide step on one MI355X.
+
+Workload (default): the turbulent pipe 192x192x1152, R = 90, Re_tau ~ 181
+shape (u* = 0.00388), log-law start, trigger force with 12 seeded amplitudes
+active for steps < 5000, FP32 deviation storage, halfway bounce-back.  One
+"step" is one time step of the whole pipe: the fused stream-collide kernel,
+plus the FP64 velocity-statistics sampling every 100 steps.
+
+Prints one JSON line: MLUPS (fluid-node updates per second / 1e6), the HBM
+roofline of the step kernel (216 algorithmic bytes per fluid-node update,
+timed with HIP events on the library's stream), and the FP64 oracle timed on
+the host cores over a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SAMPLE_EVERY = 100
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_device.h", "lbm_kernels.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2405_12082_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = rec.get(f"{workload}:{storage}")
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, amps, seconds=12.0):
+    """The FP64 oracle (as it stands) on a z-slab of the same pipe: same
+    cross-section, parameters and forcing, nz = 48."""
+    from oracle import oracle as O
+    c = dict(cfg)
+    c["nz"] = 48
+    p = O.Pipe(O.make_config(**c), amps)
+    p.step(1)
+    nf = p.n_fluid
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < seconds:
+        p.step(2)
+        steps += 2
+    dt = time.perf_counter() - t0
+    return {"value": nf * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{c['nx']}x{c['ny']}x{c['nz']} slab of the same pipe (R={c['radius']}), "
+                      f"{steps} steps, {nf} fluid nodes, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="turbulent")
+    ap.add_argument("--storage", type=int, default=0, help="0: FP32, 1: FP16 deviations")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="run this many steps only (for profiler runs) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the stepper runs one pipe per GPU); --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    P.lib()
+    cfg = LI.preset(args.workload)
+    cfg["storage"] = args.storage
+    cfg["block"] = args.block
+    cfg["zchunk"] = args.zchunk
+    amps = LI.preset_amplitudes(cfg)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        pipe = P.Pipe(cfg, amps, stream=stream)
+        if args.profile_steps:
+            pipe.step(args.profile_steps)
+            torch.cuda.synchronize()
+            print(json.dumps({"profile_steps": args.profile_steps, "workload": args.workload}))
+            return
+        nf = pipe.n_fluid
+        pipe.step(args.warmup)
+        torch.cuda.synchronize()
+
+        # timed region: K steps, velocity statistics sampled every 100 steps
+        ev_pairs = []
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_start.record(stream)
+        for s in range(args.steps):
+            if s % 10 == 5:  # bracket every tenth step kernel with events
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                pipe.step(1)
+                b.record(stream)
+                ev_pairs.append((a, b))
+            else:
+                pipe.step(1)
+            if (pipe.step_index % SAMPLE_EVERY) == 0:
+                pipe.profile_accumulate()
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_total = t_start.elapsed_time(t_end)
+        kern_ms = [a.elapsed_time(b) for a, b in ev_pairs]
+        diag = pipe.diagnostics()
+    finite = bool(np.all(diag[:, 4] == 0) and np.all(np.isfinite(diag[:, :4])))
+    ms_step = max(ms_total, wall * 1e3) / args.steps
+    mlups = nf * cfg["batch"] / (ms_step * 1e-3) / 1e6
+    lay = pipe.layout
+    bpu = int(lay.bytes_per_update)
+    kavg_ms = float(np.mean(kern_ms)) if kern_ms else float("nan")
+    alg_bytes = nf * cfg["batch"] * bpu
+    achieved = alg_bytes / (kavg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.storage)
+    out = {
+        "metric": "MLUPS + % HBM roofline (D3Q27 MRT fwd); adjoint/fwd cost ratio",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == 0 else "f32 compute, f16 storage",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload} pipe {cfg['nx']}x{cfg['ny']}x{cfg['nz']} R={cfg['radius']}",
+                   "fluid_nodes": nf, "batch": cfg["batch"], "storage": "fp32" if args.storage == 0 else "fp16",
+                   "tau": round(cfg["tau"], 6), "n_modes": cfg["n_modes"], "force_off_step": cfg["force_off_step"],
+                   "sample_every": SAMPLE_EVERY, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step", "kernel_avg_ms": round(kavg_ms, 5),
+                     "bytes_per_update": bpu, "kernel_samples": len(kern_ms)},
+        "state_finite": finite,
+        "mass": float(diag[0, 0]),
+    }
+    if not args.no_cpu_baseline:
+        c1 = dict(cfg)
+        out["cpu_baseline"] = cpu_baseline(c1, amps[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) D3Q27 MRT pipe-flow stepper.
+ *
+ * The method is the lattice Boltzmann scheme of Magacho, Moriconi &
+ * Loureiro, "Persistence of large scale coherent structures in a turbulent
+ * pipe flow through an improved lattice Boltzmann approach"
+ * (arXiv:2405.12082): collide (Eqs. (collision), (mrt), (m*), (Rmrti),
+ * (k*f*) of the appendix: multiple-relaxation-time collision in the raw
+ * moment basis of Eq. (Mmatrix), relaxation matrix Eq. (lambda), sixth-order
+ * Hermite equilibrium Eq. (BoltzmannEquilibriumDistribution), Guo forcing)
+ * then stream (Eq. (streaming)), on a D3Q27 lattice inside a circular pipe
+ * on a Cartesian mask, axially periodic, driven by a constant body force
+ * plus the divergence-free trigger force of Eq. (TurbForce) (Section II.B).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: 0 (LBM_OK) on success, a negative LBM_E* code on error.
+ *    Nothing throws across this boundary.  After an error on a context,
+ *    lbm_last_error() returns a message.  HIP errors are sticky: once a
+ *    call returned LBM_EHIP, every later call on that context does too.
+ *  - Memory: the library never allocates device memory.  The caller passes
+ *    one device workspace (size from lbm_workspace_bytes) and device output
+ *    buffers, and keeps them alive while the context lives.  Host arrays
+ *    passed in are copied before the call returns.
+ *  - Streams: every device operation is enqueued on the stream given to
+ *    lbm_init (a hipStream_t passed as void*).  Calls return once the work
+ *    is enqueued, except lbm_init and the calls that return host data
+ *    (lbm_diagnostics, lbm_profile_read), which synchronise that stream.
+ *  - Threading: one context per stream; calls on one context must not
+ *    overlap.
+ *  - Geometry: node (x, y, z), 0 <= x < nx etc.; the pipe axis is at
+ *    ((nx-1)/2, (ny-1)/2) and a node is fluid iff its distance to the axis
+ *    is < radius (radius <= 0: every node is fluid, a fully periodic box).
+ *    All axes wrap periodically.  Dense arrays exchanged with the caller
+ *    use x fastest: [b][z][y][x]; solid nodes read and write as 0.
+ *  - Populations: the library stores deviations g_i = f_i - w_i from the
+ *    lattice weights (Eq. (omegas)), in FP32 or FP16 (storage field).
+ *  - Velocity set order: 0 rest; 1-6 (+x,-x,+y,-y,+z,-z); 7-10 xy edges
+ *    (++,-+,+-,--); 11-14 xz edges; 15-18 yz edges; 19-26 corners, as in
+ *    the appendix.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1, /* invalid argument or configuration */
+    LBM_ENOMEM = -2, /* workspace too small */
+    LBM_EHIP = -3,   /* HIP runtime error (sticky) */
+    LBM_ESTATE = -4, /* call not valid in the current state */
+    LBM_ENAN = -5    /* non-finite populations detected */
+};
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+typedef struct {
+    int32_t nx, ny, nz;   /* per-pipe box, each >= 1 */
+    int32_t batch;        /* independent pipes of the same geometry, >= 1 */
+    double radius;        /* pipe radius in lattice units (<= 0: no wall) */
+    double tau;           /* relaxation time; omega = 1/tau on moments 4..8 (Eq. (lambda)), > 0.5 */
+    double accel_z;       /* constant body acceleration h along z (Section II.B: force density rho h) */
+    int32_t n_modes;      /* trigger-force modes m = 1..n_modes (0..6), each cos and sin */
+    double kz;            /* streamwise wavenumber k_z of Eq. (TurbForce) */
+    double kappa;         /* radial/azimuthal split kappa of Eq. (TurbForce) */
+    double l0_frac;       /* l_0 / R: force active for R - l0 - l <= r <= R - l0 */
+    double l_frac;        /* l / R */
+    double period;        /* forcing period T in steps: time factor sin(2 pi n / T) */
+    int64_t force_off_step; /* trigger force applied for steps n < force_off_step */
+    int32_t storage;      /* 0: FP32 deviations; 1: FP16 deviations scaled by 2^k ~ 1/w_i */
+    int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1)) */
+    int32_t pattern;      /* 0: two buffers (A/B) */
+    int32_t init;         /* 0: rest (g = 0); 1: log-law mean profile, f = f^eq(1, u_z(r)) */
+    double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
+    int32_t adjoint;      /* nonzero: the workspace also holds the adjoint buffers */
+    int32_t block;        /* threads per block: 64, 128, 256 (0 = default) */
+    int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
+} lbm_config;
+
+/* Layout facts of a configuration (host only, no GPU needed). */
+typedef struct {
+    int64_t n_fluid_columns; /* fluid (x, y) columns of one cross-section */
+    int64_t plane_pitch;     /* stored elements per (pipe, population, z) plane */
+    int64_t n_fluid_nodes;   /* fluid nodes of one pipe */
+    int64_t state_bytes;     /* bytes of one population state (all pipes) */
+    int64_t workspace_bytes; /* bytes lbm_init needs */
+    int64_t bytes_per_update;/* algorithmic HBM bytes per fluid-node update of lbm_step */
+} lbm_layout;
+
+/* Check a configuration and report its layout.  Host only.
+ * Errors: LBM_EINVAL for an invalid configuration (cfg NULL, sizes < 1,
+ * tau <= 0.5, n_modes outside 0..6, period <= 0 with n_modes > 0, a
+ * cross-section with no fluid column, radius > (min(nx,ny)-1)/2, unknown
+ * storage/wall/pattern/init values, block/zchunk out of range). */
+int lbm_describe(const lbm_config *cfg, lbm_layout *out);
+
+/* Device workspace size lbm_init needs for cfg.  Host only. */
+int lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes);
+
+/* Create a context: validates cfg, builds the z-invariant column tables
+ * (fluid-column list, neighbour table, trigger-force shapes from
+ * Eq. (TurbForce) with the per-pipe amplitudes) on the host, copies them
+ * into the workspace and writes the initial state (step 0).
+ *  amps:      host [batch][2*n_modes] doubles, mode m = p/2 + 1 with phase
+ *             0 (even p, cos) or pi/(2m) (odd p, sin); amplitude of the
+ *             acceleration (replaces h*A_0).  May be NULL if n_modes == 0.
+ *  workspace: device memory of at least lbm_workspace_bytes, 256-byte aligned.
+ *  stream:    hipStream_t (NULL: the default stream).
+ * Synchronises the stream.  *out is NULL on error. */
+int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t bytes,
+             void *stream, lbm_ctx **out);
+
+/* Enqueue n >= 0 time steps (collide then stream, Eqs. (collision) and
+ * (streaming)), one fused stream-collide kernel per step.  Async. */
+int lbm_step(lbm_ctx *ctx, int32_t n);
+
+/* Enqueue n steps by replaying a captured HIP graph of k steps (k even,
+ * 2 <= k <= 1024; captured on first use and on a change of k) plus eager
+ * launches for the remainder.  Async.  Same results as lbm_step. */
+int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
+
+/* Current step index n (the state held is f^n, before its collision). */
+int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
+
+/* Density and velocity of the current state f^n, Eqs. (macroscopic_rho) and
+ * (macroscopic_u), with u = j/rho + a(x, n)/2 (a: the body acceleration of
+ * step n).  Device outputs: rho [batch][nz][ny][nx], u [batch][3][nz][ny][nx]
+ * (FP32).  Either pointer may be NULL.  Async. */
+int lbm_moments(lbm_ctx *ctx, float *rho, float *u);
+
+/* Deviations g_i = f_i - w_i of the current state f^n.  Device output
+ * [batch][27][nz][ny][nx] FP32.  Async. */
+int lbm_populations(lbm_ctx *ctx, float *g);
+
+/* Replace the state by the given deviations (device [batch][27][nz][ny][nx]
+ * FP32; solid entries ignored) and set the step index.  Async. */
+int lbm_set_populations(lbm_ctx *ctx, const float *g, int64_t step);
+
+/* FP64 sums of the current state per pipe: host [batch][5] =
+ * {sum rho, sum j_x, sum j_y, sum j_z, number of non-finite populations}
+ * over fluid nodes, j = sum_i c_i f_i.  Two-pass fixed-order reduction
+ * (bitwise reproducible).  Synchronises.  Returns LBM_ENAN (after filling
+ * the output) when any population is non-finite. */
+int lbm_diagnostics(lbm_ctx *ctx, double *host_out);
+
+/* Add the current state's streamwise-velocity power sums to the per-column
+ * FP64 accumulators: sum over z of u_z, u_z^2, u_z^3, u_z^4 and the count
+ * (statistics of Eq. (urmsformula), pooled over z).  Async. */
+int lbm_profile_accumulate(lbm_ctx *ctx);
+/* Zero the accumulators.  Async. */
+int lbm_profile_reset(lbm_ctx *ctx);
+/* Copy the accumulators to host [batch][ny][nx][5] (solid columns 0).
+ * Synchronises. */
+int lbm_profile_read(lbm_ctx *ctx, double *host_out);
+
+/* Bytes of one saved state (populations, all pipes). */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+/* Copy the state to / from caller device memory of lbm_state_bytes bytes;
+ * lbm_load also sets the step index.  Async, stream-ordered. */
+int lbm_save(lbm_ctx *ctx, void *dst, int64_t *step);
+int lbm_load(lbm_ctx *ctx, const void *src, int64_t step);
+
+/* Discrete adjoint of lbm_step (requires cfg.adjoint != 0).
+ * Forward map of one step: f^{n+1} = S C(f^n, a^n), C the collision at every
+ * fluid node, S the streaming with the wall.  Objective:
+ *     J = 1/W sum_{n in [obs_begin, obs_end)} E(f^n),
+ *     E(f^n) = (1/N_f) sum_x 1/2 rho u_z^2 with u_z = j_z/rho + a_z(x, n)/2,
+ * the time-averaged streamwise kinetic energy, W = obs_end - obs_begin.
+ * The adjoint state lambda^n = dJ/df^n lives in the workspace (FP32):
+ *     lambda^c = (dC/df^c)^T S^T lambda^{c+1} + dE_c/df^c [c in window],
+ * with lambda^{N+1} = 0 for the last state N = obs_end - 1.
+ *
+ * lbm_adjoint_reset: lambda := 0, stores the window and sets the cursor c
+ * to obs_end - 1.  Async.
+ * lbm_adjoint_step: n >= 1 reverse steps.  fwd_states points to n saved
+ * states (lbm_save layout, device memory) f^{c-n+1} .. f^c in forward order,
+ * state_stride bytes apart; they are consumed last to first, each one
+ * producing lambda^c and moving the cursor to c - 1.  The gradient
+ *     dJ/d amps[b][q] += sum_x [(dC/da)^T S^T lambda^{c+1} + dE_c/da] . da(x,c)/d amps[b][q]
+ * is accumulated in FP64 into grad (device [batch][2*n_modes] doubles,
+ * caller-owned, not zeroed).  Once f^0 is consumed the gradient is complete.
+ * Errors: LBM_ESTATE if the adjoint buffers are absent, no reset was made,
+ * or the cursor would move below 0.  Async. */
+int lbm_adjoint_reset(lbm_ctx *ctx, int64_t obs_begin, int64_t obs_end);
+int lbm_adjoint_step(lbm_ctx *ctx, int32_t n, const void *fwd_states, size_t state_stride,
+                     double *grad);
+/* Objective E(f^n) of the current forward state per pipe, FP64, host
+ * [batch].  Synchronises. */
+int lbm_energy(lbm_ctx *ctx, double *host_out);
+
+/* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
+const char *lbm_last_error(const lbm_ctx *ctx);
+/* Release the context (not the caller's memory).  Synchronises its stream. */
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

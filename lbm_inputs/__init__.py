@@ -49,6 +49,63 @@ def uniform01(seed: int, n: int) -> np.ndarray:
     return out
 
 
+_GOLDEN = 0x9E3779B97F4A7C15
+_MIX1 = 0xBF58476D1CE4E5B9
+_MIX2 = 0x94D049BB133111EB
+
+
+def hash_uniform(seed: int, idx) -> np.ndarray:
+    """Counter-based U[0,1): element ``idx`` of the SplitMix64 sequence seeded
+    with ``seed`` (equal to ``uniform01(seed, n)[idx]``), vectorised."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _MASK64) + (idx + np.uint64(1)) * np.uint64(_GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_MIX1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_MIX2)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def _signed(v: int) -> int:
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def hash_uniform_torch(seed: int, idx):
+    """Same sequence as :func:`hash_uniform` for an int64 torch tensor of
+    indices, on the tensor's device (wrapping int64 arithmetic, logical shifts)."""
+    import torch
+
+    def lsr(z, s):
+        return (z >> s) & ((1 << (64 - s)) - 1)
+
+    z = (idx + 1) * _signed(_GOLDEN) + _signed(seed & _MASK64)
+    z = (z ^ lsr(z, 30)) * _signed(_MIX1)
+    z = (z ^ lsr(z, 27)) * _signed(_MIX2)
+    z = z ^ lsr(z, 31)
+    return lsr(z, 11).to(torch.float64) * (1.0 / (1 << 53))
+
+
+#: per-direction magnitude of the synthetic population deviations, by shell
+#: |c|^2 = 0, 1, 2, 3 (input shaping only)
+DEV_SHELL_SCALE = (0.3, 0.075, 0.01875, 0.0046875)
+_SHELL = np.array([0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3])
+
+
+def deviation_scale(i):
+    """Magnitude of synthetic deviations for direction(s) i (appendix order)."""
+    return np.asarray(DEV_SHELL_SCALE)[_SHELL[np.asarray(i)]]
+
+
+def random_deviations(seed: int, shape, amp: float = 0.02) -> np.ndarray:
+    """Seeded population deviations [27][...] (float32): amp * scale_i * U(-1, 1),
+    element (i, rest) taken from the counter-based stream at its flat index."""
+    n = int(np.prod(shape))
+    idx = np.arange(27 * n, dtype=np.uint64)
+    u = hash_uniform(seed, idx).reshape((27,) + tuple(shape))
+    sc = deviation_scale(np.arange(27)).reshape((27,) + (1,) * len(shape))
+    return (amp * sc * (2.0 * u - 1.0)).astype(np.float32)
+
+
 def amplitude_unit(u_tau: float, period: float) -> float:
     """Acceleration per unit dimensionless amplitude: u_b * pi / T.
 

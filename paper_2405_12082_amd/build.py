@@ -1,0 +1,50 @@
+"""Build the HIP library ``liblbm.so`` for gfx950 (in-tree, next to this file).
+
+hipcc cross-compiles without a GPU.  Packed-FP32 instructions are disabled
+(-packed-fp32-ops) so the compiler emits plain VALU FP32 arithmetic.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liblbm.so")
+SOURCES = ["lbm_runtime.hip", "lbm_kernels.hip", "lbm_adjoint.hip"]
+ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc_flags():
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+
+
+def build(verbose: bool = False, jobs: int = 3) -> str:
+    csrc = os.path.join(HERE, "csrc")
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(csrc, os.path.splitext(src)[0] + ".o")
+        cmd = ["hipcc", *hipcc_flags(), "-c", os.path.join(csrc, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(obj)
+        if len(procs) >= jobs:
+            if procs.pop(0).wait() != 0:
+                raise RuntimeError(f"hipcc failed on {src}")
+    for p in procs:
+        if p.wait() != 0:
+            raise RuntimeError("hipcc failed")
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,80 @@
+// lbm_internal.h -- kernel argument blocks and launchers shared by the
+// runtime (lbm_runtime.hip) and the kernels (lbm_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// z-invariant geometry and forcing tables, all in the caller's workspace
+struct Geom {
+    int ncol;        // fluid columns of one cross-section
+    int P;           // plane pitch (elements), multiple of 64
+    int nx, ny, nz, B;
+    int pstride;     // nz * P: elements between populations of one pipe
+    long long pipe;  // 27 * nz * P: elements between pipes
+    const int *nbr;          // [9][P]: column of (x+dx, y+dy), -1 if solid
+    const unsigned *colxy;   // [P]: x | y << 16
+    const float *fshape;     // [B][3][P]: trigger shape sums (P_x, P_y, Q)
+    const float *ztab;       // [2][nz]: cos, sin(k_z 2 pi z / L)
+    const float *sigma;      // [n_sigma]: sin(2 pi n / T) for n < force_off_step
+    long long n_sigma;
+    const long long *step_dev;  // device step counter (graph-safe)
+    float omega, accel_z;
+};
+
+// tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe
+struct Tiles {
+    int block, zchunk, nkb, nzc;
+    long long count() const { return (long long)nkb * nzc; }
+};
+
+enum ObserveFlags {
+    OBS_MOMENTS = 1,   // dense rho / u outputs
+    OBS_POPS = 2,      // dense population deviations
+    OBS_DIAG = 4,      // FP64 mass / momentum / non-finite partials per tile
+    OBS_PROFILE = 8,   // FP64 per-column u_z power sums per z-chunk
+    OBS_ENERGY = 16,   // FP64 1/2 rho u_z^2 partials per tile
+};
+
+struct ObserveArgs {
+    int flags;
+    float *rho;         // [B][nz][ny][nx]
+    float *u;           // [B][3][nz][ny][nx]
+    float *pops;        // [B][27][nz][ny][nx]
+    double *diag_part;  // [tiles][5]
+    double *prof_part;  // [B][nzc][P][5]
+    double *energy_part;// [tiles]
+};
+
+// launchers (return the hipError_t of the launch)
+hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
+                       hipStream_t s);
+hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
+                          int step_off, hipStream_t s);
+hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s);
+hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s);
+hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
+hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
+hipError_t launch_reduce_profile(const Geom &g, const Tiles &t, const double *part, double *acc, hipStream_t s);
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
+hipError_t launch_set_step(long long *step_dev, long long value, int add, hipStream_t s);
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// adjoint
+struct AdjointArgs {
+    const void *state;     // saved forward state holding S^T f^c
+    const float *lam_in;   // lambda^{c+1} (stored plainly: lambda_i at its own node)
+    float *lam_out;        // lambda^c
+    double *grad_part;     // [B][nzc][P][3]: FP64 per-column force sensitivities
+    long long cursor;      // c
+    int in_window;         // c in [obs_begin, obs_end)
+    int has_next;          // c + 1 was collided (lambda^{c+1} nonzero)
+    double energy_weight;  // 1 / (W N_f)
+};
+hipError_t launch_adjoint(int storage, const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s);
+hipError_t launch_project_grad(const Geom &g, const Tiles &t, const double *grad_part, double *colsum,
+                               const double *mode_shape, int nq, double sigma, double *grad, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,429 @@
+// lbm_kernels.hip -- gfx950 kernels of the D3Q27 MRT pipe stepper.
+//
+// Storage: populations are kept as deviations g_i = f_i - w_i in a
+// section-compressed structure-of-arrays layout, state[b][i][z][k], where k
+// runs over the fluid (x, y) columns of the z-invariant cross-section (no
+// solid node is stored) and each (b, i, z) plane has a pitch P (multiple of
+// 64 elements).  Between steps the buffer holds the post-collision values
+// g*(n-1) = S^T g(n) (S: streaming with the wall), so a step is one pull
+// gather, one collision and one aligned store per node: 27 loads and 27
+// stores, 216 B (FP32) or 108 B (FP16) of HBM traffic per fluid-node update.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------- helpers
+struct TileCoord {
+    int b, zc, k, kb;
+};
+__device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    TileCoord c;
+    c.kb = tile % t.nkb;
+    const int rest = tile / t.nkb;
+    c.zc = rest % t.nzc;
+    c.b = rest / t.nzc;
+    c.k = c.kb * block + threadIdx.x;
+    return c;
+}
+
+__device__ __forceinline__ void load_columns(const Geom &g, int k, int (&col)[9])
+{
+#pragma unroll
+    for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
+}
+
+__device__ __forceinline__ float sigma_of(const Geom &g, long long n)
+{
+    return (n >= 0 && n < g.n_sigma) ? g.sigma[n] : 0.f;
+}
+
+__device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : z - 1; }
+__device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
+
+// ---------------------------------------------------------------- step
+// One time step of every fluid node: pull gather (streaming + bounce-back)
+// of g(n) from S^T g(n), collision at a(x, n), aligned store of g*(n).
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
+                                                 T *__restrict__ dst, int step_off)
+{
+    const TileCoord tc = decode_tile(t, BLOCK);
+    const int k = tc.k;
+    if (k >= g.ncol) return;
+    int col[9];
+    load_columns(g, k, col);
+    const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
+    const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
+    const long long n = *g.step_dev + step_off;
+    const float sig = sigma_of(g, n);
+    const T *pin = src + (size_t)tc.b * g.pipe;
+    T *pout = dst + (size_t)tc.b * g.pipe;
+    const int z0 = tc.zc * t.zchunk;
+    const int z1 = min(z0 + t.zchunk, g.nz);
+    for (int z = z0; z < z1; ++z) {
+        float v[27];
+        gather<T>(pin, g.pstride, g.P, col, k, z, wrap_m(z, g.nz), wrap_p(z, g.nz), v);
+        const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
+        const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
+        const Moments m = moments_of(v);
+        float ux, uy, uz;
+        const CollideCtx c = collide_setup(m, ax, ay, az, g.omega, ux, uy, uz);
+        post_collision_all(c, v);
+        store_all<T>(pout, g.pstride, z * g.P + k, v);
+    }
+}
+
+// ---------------------------------------------------------------- observe
+// Gather of the current state g(n) and its moments: dense outputs and FP64
+// partial sums for the diagnostics, the velocity statistics and the energy.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int BLOCK, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [BLOCK/64][NV] */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[wid * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < BLOCK / 64; ++w)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] += lds[w * NV + q];
+}
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, const T *__restrict__ state,
+                                                    const ObserveArgs o, int step_off)
+{
+    const TileCoord tc = decode_tile(t, BLOCK);
+    const int k = tc.k;
+    const bool active = k < g.ncol;
+    const long long n = *g.step_dev + step_off;
+    const float sig = sigma_of(g, n);
+    double dsum[5] = {0, 0, 0, 0, 0};
+    double esum[1] = {0};
+    double psum[4] = {0, 0, 0, 0};
+    int cnt = 0;
+    if (active) {
+        int col[9];
+        load_columns(g, k, col);
+        const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
+        const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
+        const unsigned xy = g.colxy[k];
+        const int x = xy & 0xffff, y = xy >> 16;
+        const size_t plane = (size_t)g.nx * g.ny;
+        const T *pin = state + (size_t)tc.b * g.pipe;
+        const int z0 = tc.zc * t.zchunk;
+        const int z1 = min(z0 + t.zchunk, g.nz);
+        for (int z = z0; z < z1; ++z) {
+            float v[27];
+            gather<T>(pin, g.pstride, g.P, col, k, z, wrap_m(z, g.nz), wrap_p(z, g.nz), v);
+            const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
+            const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
+            const Moments m = moments_of(v);
+            const float rho = 1.f + m.dr;
+            const float inv = 1.f / rho;
+            const float ux = m.jx * inv + 0.5f * ax, uy = m.jy * inv + 0.5f * ay, uz = m.jz * inv + 0.5f * az;
+            const size_t node = ((size_t)tc.b * g.nz + z) * plane + (size_t)y * g.nx + x;
+            if (o.flags & OBS_MOMENTS) {
+                if (o.rho) o.rho[node] = rho;
+                if (o.u) {
+                    const size_t ub = ((size_t)tc.b * 3 * g.nz + z) * plane + (size_t)y * g.nx + x;
+                    const size_t us = (size_t)g.nz * plane;
+                    o.u[ub] = ux;
+                    o.u[ub + us] = uy;
+                    o.u[ub + 2 * us] = uz;
+                }
+            }
+            if (o.flags & OBS_POPS) {
+                const size_t pb = ((size_t)tc.b * 27 * g.nz + z) * plane + (size_t)y * g.nx + x;
+                const size_t ps = (size_t)g.nz * plane;
+#pragma unroll
+                for (int i = 0; i < 27; ++i) o.pops[pb + i * ps] = v[i];
+            }
+            if (o.flags & OBS_DIAG) {
+                dsum[0] += (double)m.dr;
+                dsum[1] += (double)m.jx;
+                dsum[2] += (double)m.jy;
+                dsum[3] += (double)m.jz;
+                int bad = 0;
+#pragma unroll
+                for (int i = 0; i < 27; ++i) bad += !isfinite(v[i]);
+                dsum[4] += (double)bad;
+            }
+            if (o.flags & OBS_PROFILE) {
+                const double w = (double)uz;
+                psum[0] += w;
+                psum[1] += w * w;
+                psum[2] += w * w * w;
+                psum[3] += w * w * w * w;
+            }
+            if (o.flags & OBS_ENERGY) esum[0] += 0.5 * (double)rho * (double)uz * (double)uz;
+            ++cnt;
+        }
+        if (o.flags & OBS_PROFILE) {
+            double *pp = o.prof_part + (((size_t)tc.b * t.nzc + tc.zc) * g.P + k) * 5;
+            pp[0] = psum[0];
+            pp[1] = psum[1];
+            pp[2] = psum[2];
+            pp[3] = psum[3];
+            pp[4] = (double)cnt;
+        }
+    }
+    const size_t tile = ((size_t)tc.b * t.nzc + tc.zc) * t.nkb + tc.kb;
+    if (o.flags & OBS_DIAG) {
+        __shared__ double lds[(BLOCK / 64) * 5];
+        // fluid-node count enters sum rho = N + sum dr
+        dsum[0] += (double)cnt;
+        block_sum<BLOCK, 5>(dsum, lds);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 5; ++q) o.diag_part[tile * 5 + q] = dsum[q];
+        __syncthreads();
+    }
+    if (o.flags & OBS_ENERGY) {
+        __shared__ double lde[BLOCK / 64];
+        block_sum<BLOCK, 1>(esum, lde);
+        if (threadIdx.x == 0) o.energy_part[tile] = esum[0];
+    }
+}
+
+// fixed-order reduction of per-tile partials: one block per pipe
+template <int NV>
+__global__ __launch_bounds__(256) void k_reduce_tiles(const double *__restrict__ part, long long tiles_per_pipe,
+                                                      double *__restrict__ out)
+{
+    __shared__ double lds[256 * NV];
+    const int b = blockIdx.x;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    for (long long t = threadIdx.x; t < tiles_per_pipe; t += 256)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] += part[((size_t)b * tiles_per_pipe + t) * NV + q];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[threadIdx.x * NV + q] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) lds[threadIdx.x * NV + q] += lds[(threadIdx.x + s) * NV + q];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) out[b * NV + q] = lds[q];
+}
+
+// acc[b][k][5] += sum over z-chunks of the per-chunk partials, in order
+__global__ __launch_bounds__(256) void k_reduce_profile(const double *__restrict__ part, double *__restrict__ acc,
+                                                        int nzc, int P, int ncol, int B)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long long)B * ncol) return;
+    const int b = (int)(idx / ncol), k = (int)(idx % ncol);
+    double s[5] = {0, 0, 0, 0, 0};
+    for (int zc = 0; zc < nzc; ++zc) {
+        const double *p = part + (((size_t)b * nzc + zc) * P + k) * 5;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s[q] += p[q];
+    }
+    double *a = acc + ((size_t)b * P + k) * 5;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a[q] += s[q];
+}
+
+// ---------------------------------------------------------------- state writers
+// The buffer holds S^T g: slot j of node y is g_j(y + c_j) when y + c_j is
+// fluid, else g_opp(j)(y) (inverse of the bounce-back pull).
+template <typename T, int J = 0>
+__device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&col)[9], const float *u0, int k,
+                                           int z, const Axis &zero, const Axis &own)
+{
+    constexpr int cx = CX(J), cy = CY(J);
+    const int sc = col[NSLOT(cx, cy)];
+    float v;
+    if (sc >= 0) {
+        const Axis a = axis_factors(u0[sc]);
+        v = feq_dev<J>(0.f, zero, zero, a);
+    } else {
+        v = feq_dev<OPP(J)>(0.f, zero, zero, own);
+    }
+    Codec<T>::template store<J>(pipe + J * g.pstride + z * g.P + k, v);
+    if constexpr (J + 1 < 27) init_slots<T, J + 1>(pipe, g, col, u0, k, z, zero, own);
+}
+
+// Initial state f^0 = f^eq(1, (0, 0, u0(r))) (u0 = 0: rest)
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restrict__ u0, T *__restrict__ state)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = (long long)g.B * g.nz * g.ncol;
+    if (idx >= total) return;
+    const int k = (int)(idx % g.ncol);
+    const long long r = idx / g.ncol;
+    const int z = (int)(r % g.nz), b = (int)(r / g.nz);
+    int col[9];
+    load_columns(g, k, col);
+    const Axis zero = axis_factors(0.f), own = axis_factors(u0[k]);
+    init_slots<T>(state + (size_t)b * g.pipe, g, col, u0, k, z, zero, own);
+}
+
+template <typename T, int J = 0>
+__device__ __forceinline__ void set_slots(T *pipe, const Geom &g, const int (&col)[9], const float *src, int k, int z,
+                                          size_t plane, size_t popstride)
+{
+    constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
+    const int sc = col[NSLOT(cx, cy)];
+    float v;
+    if (sc >= 0) {
+        const unsigned xy = g.colxy[sc];
+        const int zs = cz == 0 ? z : (cz > 0 ? (z == g.nz - 1 ? 0 : z + 1) : (z == 0 ? g.nz - 1 : z - 1));
+        v = src[J * popstride + (size_t)zs * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
+    } else {
+        const unsigned xy = g.colxy[k];
+        v = src[OPP(J) * popstride + (size_t)z * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
+    }
+    Codec<T>::template store<J>(pipe + J * g.pstride + z * g.P + k, v);
+    if constexpr (J + 1 < 27) set_slots<T, J + 1>(pipe, g, col, src, k, z, plane, popstride);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_set_pops(const Geom g, const float *__restrict__ pops, T *__restrict__ state)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = (long long)g.B * g.nz * g.ncol;
+    if (idx >= total) return;
+    const int k = (int)(idx % g.ncol);
+    const long long r = idx / g.ncol;
+    const int z = (int)(r % g.nz), b = (int)(r / g.nz);
+    int col[9];
+    load_columns(g, k, col);
+    const size_t plane = (size_t)g.nx * g.ny, popstride = (size_t)g.nz * plane;
+    set_slots<T>(state + (size_t)b * g.pipe, g, col, pops + (size_t)b * 27 * popstride, k, z, plane, popstride);
+}
+
+__global__ void k_fill(uint32_t *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+__global__ void k_copy(uint4 *dst, const uint4 *src, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+__global__ void k_set_step(long long *p, long long v, int add)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = add ? *p + v : v;
+}
+
+// ---------------------------------------------------------------- launchers
+static int grid_of(const Tiles &t, int B) { return (int)(t.count() * B); }
+
+template <typename T>
+static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
+{
+    const dim3 grid(grid_of(t, g.B));
+    switch (t.block) {
+    case 64: hipLaunchKernelGGL((k_step<T, 64>), grid, dim3(64), 0, s, g, t, (const T *)src, (T *)dst, off); break;
+    case 128: hipLaunchKernelGGL((k_step<T, 128>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off); break;
+    default: hipLaunchKernelGGL((k_step<T, 256>), grid, dim3(256), 0, s, g, t, (const T *)src, (T *)dst, off); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
+{
+    return storage == 1 ? step_t<__half>(g, t, src, dst, off, s) : step_t<float>(g, t, src, dst, off, s);
+}
+
+hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off,
+                          hipStream_t s)
+{
+    const dim3 grid(grid_of(t, g.B));
+    if (storage == 1)
+        hipLaunchKernelGGL((k_observe<__half, 256>), grid, dim3(256), 0, s, g, t, (const __half *)state, o, off);
+    else
+        hipLaunchKernelGGL((k_observe<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)state, o, off);
+    return hipGetLastError();
+}
+
+static dim3 node_grid(const Geom &g)
+{
+    const long long total = (long long)g.B * g.nz * g.ncol;
+    return dim3((unsigned)((total + 255) / 256));
+}
+
+hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s)
+{
+    if (storage == 1)
+        hipLaunchKernelGGL((k_init<__half>), node_grid(g), dim3(256), 0, s, g, u0, (__half *)state);
+    else
+        hipLaunchKernelGGL((k_init<float>), node_grid(g), dim3(256), 0, s, g, u0, (float *)state);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s)
+{
+    if (storage == 1)
+        hipLaunchKernelGGL((k_set_pops<__half>), node_grid(g), dim3(256), 0, s, g, pops, (__half *)state);
+    else
+        hipLaunchKernelGGL((k_set_pops<float>), node_grid(g), dim3(256), 0, s, g, pops, (float *)state);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reduce_tiles<5>), dim3(g.B), dim3(256), 0, s, part, t.count(), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reduce_tiles<1>), dim3(g.B), dim3(256), 0, s, part, t.count(), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_profile(const Geom &g, const Tiles &t, const double *part, double *acc, hipStream_t s)
+{
+    const long long n = (long long)g.B * g.ncol;
+    hipLaunchKernelGGL(k_reduce_profile, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, acc, t.nzc, g.P,
+                       g.ncol, g.B);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(void *p, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    const size_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, (uint4 *)dst,
+                       (const uint4 *)src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(long long *p, long long v, int add, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, p, v, add);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,649 @@
+// lbm_runtime.hip -- host runtime and C-ABI of the D3Q27 MRT pipe stepper.
+//
+// Builds the z-invariant tables of the pipe on the host (fluid-column list,
+// neighbour table, trigger-force shapes of Eq. (TurbForce), log-law profile
+// of the initial state, Section II.B), carves the caller's workspace and
+// enqueues the kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kMaxModes = 6;
+constexpr long long kMaxSigma = 1LL << 24;   // longest forcing window (steps)
+constexpr int kObsZChunk = 16;               // z planes per thread for observation kernels
+constexpr int kDefaultBlock = 256;
+constexpr int kDefaultZChunk = 4;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    std::vector<int> colx, coly;   // fluid columns, row-major (y outer, x inner)
+    std::vector<int> colmap;       // [ny][nx] -> column or -1
+    int ncol = 0, P = 0;
+    Tiles step{}, obs{};
+    size_t elem = 4;               // bytes per stored population
+    size_t state_bytes = 0;
+    // workspace offsets
+    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step;
+    size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
+    size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
+    size_t total = 0;
+    long long n_sigma = 0;
+    std::string err;
+};
+
+bool fluid_xy(const lbm_config &c, int x, int y)
+{
+    if (c.radius <= 0.0) return true;
+    const double dx = x - 0.5 * (c.nx - 1), dy = y - 0.5 * (c.ny - 1);
+    return std::sqrt(dx * dx + dy * dy) < c.radius;
+}
+
+int build_layout(const lbm_config *cfg, Layout &L)
+{
+    if (!cfg) {
+        L.err = "config is NULL";
+        return LBM_EINVAL;
+    }
+    const lbm_config &c = *cfg;
+    char buf[256];
+    auto bad = [&](const char *m) {
+        L.err = m;
+        return LBM_EINVAL;
+    };
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1 || c.batch < 1) return bad("nx, ny, nz and batch must be >= 1");
+    if (c.nx > 32767 || c.ny > 32767) return bad("nx and ny must be < 32768");
+    if (!(c.tau > 0.5) || !std::isfinite(c.tau)) return bad("tau must be > 0.5");
+    if (!std::isfinite(c.accel_z)) return bad("accel_z must be finite");
+    if (c.n_modes < 0 || c.n_modes > kMaxModes) return bad("n_modes must be in 0..6");
+    if (c.n_modes > 0) {
+        if (!(c.period > 0.0)) return bad("period must be > 0 when n_modes > 0");
+        if (c.radius <= 0.0) return bad("the trigger force needs a pipe wall (radius > 0)");
+        if (!(c.l_frac > 0.0) || c.l0_frac < 0.0) return bad("l_frac must be > 0 and l0_frac >= 0");
+        if (c.force_off_step > kMaxSigma) return bad("force_off_step must be <= 2^24");
+    }
+    if (c.storage != 0 && c.storage != 1) return bad("storage must be 0 (FP32) or 1 (FP16)");
+    if (c.wall != 0) return bad("wall must be 0 (halfway bounce-back)");
+    if (c.pattern != 0) return bad("pattern must be 0 (two buffers)");
+    if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");
+    if (c.init == 1 && (c.radius <= 0.0 || !(c.u_tau >= 0.0))) return bad("log-law init needs radius > 0, u_tau >= 0");
+    if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
+        return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
+    const int block = c.block ? c.block : kDefaultBlock;
+    if (block != 64 && block != 128 && block != 256) return bad("block must be 64, 128 or 256");
+    const int zchunk = c.zchunk ? c.zchunk : kDefaultZChunk;
+    if (zchunk < 1 || zchunk > 64) return bad("zchunk must be in 1..64");
+
+    L.colmap.assign((size_t)c.nx * c.ny, -1);
+    L.colx.clear();
+    L.coly.clear();
+    for (int y = 0; y < c.ny; ++y)
+        for (int x = 0; x < c.nx; ++x)
+            if (fluid_xy(c, x, y)) {
+                L.colmap[(size_t)y * c.nx + x] = (int)L.colx.size();
+                L.colx.push_back(x);
+                L.coly.push_back(y);
+            }
+    L.ncol = (int)L.colx.size();
+    if (L.ncol == 0) return bad("the cross-section has no fluid column");
+    L.P = (int)align_up((size_t)L.ncol, 64);
+    if ((long long)27 * c.nz * L.P >= (1LL << 31)) {
+        std::snprintf(buf, sizeof buf, "pipe too large: 27*nz*pitch = %lld must be < 2^31",
+                      (long long)27 * c.nz * L.P);
+        return bad(buf);
+    }
+    L.elem = c.storage == 1 ? 2 : 4;
+    const long long pipe_elems = 27LL * c.nz * L.P;
+    L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
+    L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk};
+    L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk};
+    L.n_sigma = c.n_modes > 0 ? std::max<long long>(c.force_off_step, 0) : 0;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 1), 256);
+        return o;
+    };
+    const size_t B = (size_t)c.batch, P = (size_t)L.P;
+    L.off_state[0] = take(L.state_bytes);
+    L.off_state[1] = take(L.state_bytes);
+    L.off_nbr = take(9 * P * sizeof(int));
+    L.off_colxy = take(P * sizeof(unsigned));
+    L.off_fshape = take(B * 3 * P * sizeof(float));
+    L.off_ztab = take(2 * (size_t)c.nz * sizeof(float));
+    L.off_sigma = take((size_t)L.n_sigma * sizeof(float));
+    L.off_u0 = take(P * sizeof(float));
+    L.off_step = take(sizeof(long long));
+    const size_t obs_tiles = (size_t)L.obs.count() * B;
+    L.off_diag_part = take(obs_tiles * 5 * sizeof(double));
+    L.off_diag_out = take(B * 5 * sizeof(double));
+    L.off_prof_part = take(B * L.obs.nzc * P * 5 * sizeof(double));
+    L.off_prof_acc = take(B * P * 5 * sizeof(double));
+    L.off_energy_part = take(obs_tiles * sizeof(double));
+    L.off_energy_out = take(B * sizeof(double));
+    if (c.adjoint) {
+        const size_t lam = align_up((size_t)pipe_elems * B * sizeof(float), 256);
+        L.off_lam[0] = take(lam);
+        L.off_lam[1] = take(lam);
+        L.off_grad_part = take(B * L.obs.nzc * P * 3 * sizeof(double));
+        L.off_grad_col = take(B * P * 3 * sizeof(double));
+        L.off_modes = take((size_t)2 * kMaxModes * 3 * P * sizeof(double));
+    } else {
+        L.off_lam[0] = L.off_lam[1] = L.off_grad_part = L.off_grad_col = L.off_modes = 0;
+    }
+    L.total = off;
+    return LBM_OK;
+}
+
+// One mode of Eq. (TurbForce) at unit time factor and unit z-factor:
+// cylindrical (F_r, F_theta, F_z) without the cos/sin(k_z 2 pi z / L)
+// factors, which the kernels apply per plane.  Mode m, phase phi.
+void mode_shape(const lbm_config &c, double amp, int m, double phi, int x, int y, double out[3])
+{
+    out[0] = out[1] = out[2] = 0.0;
+    const double R = c.radius, L = (double)c.nz;
+    const double l0 = c.l0_frac * R, l = c.l_frac * R;
+    const double dx = x - 0.5 * (c.nx - 1), dy = y - 0.5 * (c.ny - 1);
+    const double r = std::sqrt(dx * dx + dy * dy);
+    if (r <= 0.0 || r < R - l0 - l || r > R - l0) return;
+    const double th = std::atan2(dy, dx), a = m * (th - phi);
+    const double arg = 2.0 * M_PI * (R - r - l0) / l;
+    const double Fr = -amp * c.kappa * (R / r) * (c.kz * l / L) * (1.0 - std::cos(arg)) * std::cos(a);
+    const double Ft = amp * (1.0 - c.kappa) * (c.kz / m) * (2.0 * M_PI * R / L) * std::sin(arg) * std::sin(a);
+    const double Fz = -amp * (R / r) * std::sin(arg) * std::cos(a);
+    out[0] = Fr * std::cos(th) - Ft * std::sin(th);
+    out[1] = Fr * std::sin(th) + Ft * std::cos(th);
+    out[2] = Fz;
+}
+
+double loglaw(const lbm_config &c, double r)
+{
+    const double nu = (c.tau - 0.5) / 3.0;
+    const double dp = (c.radius - r) * c.u_tau / nu;
+    return c.u_tau * (dp <= 10.8 ? dp : std::log(dp) / 0.4 + 5.0);
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg{};
+    Layout L;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    char *ws = nullptr;
+    Geom geom{};
+    long long step = 0;
+    int sticky = 0;
+    std::string err;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_k[2] = {0, 0};
+    // adjoint
+    bool adj_ready = false;
+    long long cursor = -1, obs_begin = 0, obs_end = 0;
+    int lam_cur = 0;
+    bool lam_nonzero = false;
+
+    void *state(long long n) const { return ws + L.off_state[n & 1]; }
+};
+
+namespace {
+
+int fail(lbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) {
+        c->err = msg;
+        if (code == LBM_EHIP) c->sticky = 1;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                                   \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail(ctx, LBM_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_));             \
+    } while (0)
+
+#define CHECK_CTX(ctx)                                                                                      \
+    do {                                                                                                    \
+        if (!(ctx)) return LBM_EINVAL;                                                                      \
+        if ((ctx)->sticky) return LBM_EHIP;                                                                 \
+    } while (0)
+
+int do_step_eager(lbm_ctx *c, int n)
+{
+    for (int j = 0; j < n; ++j)
+        HIPCHK(c, launch_step(c->cfg.storage, c->geom, c->L.step, c->state(c->step + j), c->state(c->step + j + 1), j,
+                              c->stream));
+    if (n > 0) HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
+    c->step += n;
+    return LBM_OK;
+}
+
+int observe(lbm_ctx *c, const ObserveArgs &o)
+{
+    HIPCHK(c, launch_observe(c->cfg.storage, c->geom, c->L.obs, c->state(c->step), o, 0, c->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_describe(const lbm_config *cfg, lbm_layout *out)
+{
+    Layout L;
+    const int rc = build_layout(cfg, L);
+    if (rc != LBM_OK) return rc;
+    if (out) {
+        out->n_fluid_columns = L.ncol;
+        out->plane_pitch = L.P;
+        out->n_fluid_nodes = (int64_t)L.ncol * cfg->nz;
+        out->state_bytes = (int64_t)L.state_bytes;
+        out->workspace_bytes = (int64_t)L.total;
+        out->bytes_per_update = 2 * 27 * (int64_t)L.elem;
+    }
+    return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes)
+{
+    Layout L;
+    const int rc = build_layout(cfg, L);
+    if (rc != LBM_OK) return rc;
+    if (!bytes) return LBM_EINVAL;
+    *bytes = L.total;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t bytes, void *stream, lbm_ctx **out)
+{
+    if (!out) return LBM_EINVAL;
+    *out = nullptr;
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return LBM_ENOMEM;
+    auto bail = [&](int rc) {
+        delete c;
+        return rc;
+    };
+    int rc = build_layout(cfg, c->L);
+    if (rc != LBM_OK) return bail(rc);
+    if (!workspace || bytes < c->L.total || ((uintptr_t)workspace & 255)) return bail(LBM_ENOMEM);
+    if (cfg->n_modes > 0 && !amps) return bail(LBM_EINVAL);
+    c->cfg = *cfg;
+    if (!c->cfg.block) c->cfg.block = kDefaultBlock;
+    if (!c->cfg.zchunk) c->cfg.zchunk = kDefaultZChunk;
+    c->stream = (hipStream_t)stream;
+    c->ws = (char *)workspace;
+    const lbm_config &g = c->cfg;
+    const Layout &L = c->L;
+    const size_t P = (size_t)L.P, B = (size_t)g.batch;
+
+    // neighbour table: column of (x+dx, y+dy), periodic wrap, -1 if solid
+    std::vector<int> nbr(9 * P, -1);
+    std::vector<unsigned> colxy(P, 0xffffffffu);
+    for (int k = 0; k < L.ncol; ++k) {
+        colxy[k] = (unsigned)L.colx[k] | ((unsigned)L.coly[k] << 16);
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = (L.colx[k] + dx + g.nx) % g.nx, y = (L.coly[k] + dy + g.ny) % g.ny;
+                nbr[(size_t)((dy + 1) * 3 + (dx + 1)) * P + k] = L.colmap[(size_t)y * g.nx + x];
+            }
+    }
+    // trigger-force shape sums per pipe and per column, Eq. (TurbForce)
+    std::vector<float> fshape(B * 3 * P, 0.f);
+    std::vector<double> modes((size_t)2 * kMaxModes * 3 * P, 0.0);
+    for (int k = 0; k < L.ncol; ++k)
+        for (int q = 0; q < 2 * g.n_modes; ++q) {
+            const int m = q / 2 + 1;
+            const double phi = (q % 2) ? M_PI / (2.0 * m) : 0.0;
+            double s[3];
+            mode_shape(g, 1.0, m, phi, L.colx[k], L.coly[k], s);
+            for (int d = 0; d < 3; ++d) modes[((size_t)q * 3 + d) * P + k] = s[d];
+        }
+    for (size_t b = 0; b < B; ++b)
+        for (int k = 0; k < L.ncol; ++k)
+            for (int d = 0; d < 3; ++d) {
+                double v = 0.0;
+                for (int q = 0; q < 2 * g.n_modes; ++q) v += amps[b * 2 * g.n_modes + q] * modes[((size_t)q * 3 + d) * P + k];
+                fshape[(b * 3 + d) * P + k] = (float)v;
+            }
+    std::vector<float> ztab(2 * (size_t)g.nz);
+    for (int z = 0; z < g.nz; ++z) {
+        const double ph = g.kz * 2.0 * M_PI * z / (double)g.nz;
+        ztab[z] = (float)std::cos(ph);
+        ztab[g.nz + z] = (float)std::sin(ph);
+    }
+    std::vector<float> sig((size_t)L.n_sigma);
+    for (long long n = 0; n < L.n_sigma; ++n) sig[n] = (float)std::sin(2.0 * M_PI * (double)n / g.period);
+    std::vector<float> u0(P, 0.f);
+    if (g.init == 1)
+        for (int k = 0; k < L.ncol; ++k) {
+            const double dx = L.colx[k] - 0.5 * (g.nx - 1), dy = L.coly[k] - 0.5 * (g.ny - 1);
+            u0[k] = (float)loglaw(g, std::sqrt(dx * dx + dy * dy));
+        }
+
+    char *ws = c->ws;
+    auto h2d = [&](size_t off, const void *src, size_t n) {
+        return n ? hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, c->stream) : hipSuccess;
+    };
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = h2d(L.off_nbr, nbr.data(), nbr.size() * sizeof(int));
+    if (e == hipSuccess) e = h2d(L.off_colxy, colxy.data(), colxy.size() * sizeof(unsigned));
+    if (e == hipSuccess) e = h2d(L.off_fshape, fshape.data(), fshape.size() * sizeof(float));
+    if (e == hipSuccess) e = h2d(L.off_ztab, ztab.data(), ztab.size() * sizeof(float));
+    if (e == hipSuccess) e = h2d(L.off_sigma, sig.data(), sig.size() * sizeof(float));
+    if (e == hipSuccess) e = h2d(L.off_u0, u0.data(), u0.size() * sizeof(float));
+    if (e == hipSuccess && g.adjoint) e = h2d(L.off_modes, modes.data(), modes.size() * sizeof(double));
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        return bail(LBM_EHIP);
+    }
+
+    Geom &G = c->geom;
+    G.ncol = L.ncol;
+    G.P = L.P;
+    G.nx = g.nx;
+    G.ny = g.ny;
+    G.nz = g.nz;
+    G.B = g.batch;
+    G.pstride = g.nz * L.P;
+    G.pipe = 27LL * g.nz * L.P;
+    G.nbr = (const int *)(ws + L.off_nbr);
+    G.colxy = (const unsigned *)(ws + L.off_colxy);
+    G.fshape = (const float *)(ws + L.off_fshape);
+    G.ztab = (const float *)(ws + L.off_ztab);
+    G.sigma = (const float *)(ws + L.off_sigma);
+    G.n_sigma = L.n_sigma;
+    G.step_dev = (const long long *)(ws + L.off_step);
+    G.omega = (float)(1.0 / g.tau);
+    G.accel_z = (float)g.accel_z;
+
+    c->step = 0;
+    e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
+    if (e == hipSuccess) e = launch_fill(ws + L.off_prof_acc, B * P * 5 * sizeof(double), c->stream);
+    if (e == hipSuccess) e = launch_init(g.storage, G, (const float *)(ws + L.off_u0), c->state(0), c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
+        (void)hipStreamDestroy(c->cap_stream);
+        return bail(LBM_EHIP);
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int32_t n)
+{
+    CHECK_CTX(c);
+    if (n < 0) return fail(c, LBM_EINVAL, "lbm_step: n must be >= 0");
+    return do_step_eager(c, n);
+}
+
+int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
+{
+    CHECK_CTX(c);
+    if (n < 0 || k < 2 || k > 1024 || (k & 1)) return fail(c, LBM_EINVAL, "lbm_step_graph: need n >= 0, even k in 2..1024");
+    const int par = (int)(c->step & 1);
+    if (n >= k) {
+        if (!c->graph[par] || c->graph_k[par] != k) {
+            if (c->graph[par]) {
+                (void)hipGraphExecDestroy(c->graph[par]);
+                c->graph[par] = nullptr;
+            }
+            hipGraph_t gr = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int j = 0; j < k && e == hipSuccess; ++j)
+                e = launch_step(c->cfg.storage, c->geom, c->L.step, c->state(c->step + j), c->state(c->step + j + 1), j,
+                                c->cap_stream);
+            if (e == hipSuccess) e = launch_set_step(const_cast<long long *>(c->geom.step_dev), k, 1, c->cap_stream);
+            const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return fail(c, LBM_EHIP, std::string("graph capture failed: ") +
+                                             hipGetErrorString(e != hipSuccess ? e : e2));
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e3 != hipSuccess) return fail(c, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+            c->graph[par] = ex;
+            c->graph_k[par] = k;
+        }
+        const int reps = n / k;
+        for (int r = 0; r < reps; ++r) HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
+        c->step += (long long)reps * k;
+        n -= reps * k;
+    }
+    return do_step_eager(c, n);
+}
+
+int lbm_get_step(const lbm_ctx *c, int64_t *step)
+{
+    if (!c || !step) return LBM_EINVAL;
+    *step = c->step;
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, float *rho, float *u)
+{
+    CHECK_CTX(c);
+    if (!rho && !u) return LBM_OK;
+    const size_t nodes = (size_t)c->cfg.batch * c->cfg.nz * c->cfg.ny * c->cfg.nx;
+    if (rho) HIPCHK(c, launch_fill(rho, nodes * sizeof(float), c->stream));
+    if (u) HIPCHK(c, launch_fill(u, 3 * nodes * sizeof(float), c->stream));
+    ObserveArgs o{};
+    o.flags = OBS_MOMENTS;
+    o.rho = rho;
+    o.u = u;
+    return observe(c, o);
+}
+
+int lbm_populations(lbm_ctx *c, float *g)
+{
+    CHECK_CTX(c);
+    if (!g) return fail(c, LBM_EINVAL, "lbm_populations: NULL output");
+    const size_t nodes = (size_t)c->cfg.batch * c->cfg.nz * c->cfg.ny * c->cfg.nx;
+    HIPCHK(c, launch_fill(g, 27 * nodes * sizeof(float), c->stream));
+    ObserveArgs o{};
+    o.flags = OBS_POPS;
+    o.pops = g;
+    return observe(c, o);
+}
+
+int lbm_set_populations(lbm_ctx *c, const float *g, int64_t step)
+{
+    CHECK_CTX(c);
+    if (!g || step < 0) return fail(c, LBM_EINVAL, "lbm_set_populations: NULL input or negative step");
+    c->step = step;
+    HIPCHK(c, launch_set_pops(c->cfg.storage, c->geom, g, c->state(step), c->stream));
+    HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
+    return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_ctx *c, double *host_out)
+{
+    CHECK_CTX(c);
+    if (!host_out) return fail(c, LBM_EINVAL, "lbm_diagnostics: NULL output");
+    ObserveArgs o{};
+    o.flags = OBS_DIAG;
+    o.diag_part = (double *)(c->ws + c->L.off_diag_part);
+    int rc = observe(c, o);
+    if (rc != LBM_OK) return rc;
+    double *dout = (double *)(c->ws + c->L.off_diag_out);
+    HIPCHK(c, launch_reduce_diag(c->geom, c->L.obs, o.diag_part, dout, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_out, dout, (size_t)c->cfg.batch * 5 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->cfg.batch; ++b)
+        if (host_out[b * 5 + 4] != 0.0 || !std::isfinite(host_out[b * 5])) return fail(c, LBM_ENAN, "non-finite populations");
+    return LBM_OK;
+}
+
+int lbm_energy(lbm_ctx *c, double *host_out)
+{
+    CHECK_CTX(c);
+    if (!host_out) return fail(c, LBM_EINVAL, "lbm_energy: NULL output");
+    ObserveArgs o{};
+    o.flags = OBS_ENERGY;
+    o.energy_part = (double *)(c->ws + c->L.off_energy_part);
+    int rc = observe(c, o);
+    if (rc != LBM_OK) return rc;
+    double *eout = (double *)(c->ws + c->L.off_energy_out);
+    HIPCHK(c, launch_reduce_energy(c->geom, c->L.obs, o.energy_part, eout, c->stream));
+    HIPCHK(c, hipMemcpyAsync(host_out, eout, (size_t)c->cfg.batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double nf = (double)c->L.ncol * c->cfg.nz;
+    for (int b = 0; b < c->cfg.batch; ++b) host_out[b] /= nf;
+    return LBM_OK;
+}
+
+int lbm_profile_accumulate(lbm_ctx *c)
+{
+    CHECK_CTX(c);
+    ObserveArgs o{};
+    o.flags = OBS_PROFILE;
+    o.prof_part = (double *)(c->ws + c->L.off_prof_part);
+    int rc = observe(c, o);
+    if (rc != LBM_OK) return rc;
+    HIPCHK(c, launch_reduce_profile(c->geom, c->L.obs, o.prof_part, (double *)(c->ws + c->L.off_prof_acc), c->stream));
+    return LBM_OK;
+}
+
+int lbm_profile_reset(lbm_ctx *c)
+{
+    CHECK_CTX(c);
+    HIPCHK(c, launch_fill(c->ws + c->L.off_prof_acc, (size_t)c->cfg.batch * c->L.P * 5 * sizeof(double), c->stream));
+    return LBM_OK;
+}
+
+int lbm_profile_read(lbm_ctx *c, double *host_out)
+{
+    CHECK_CTX(c);
+    if (!host_out) return fail(c, LBM_EINVAL, "lbm_profile_read: NULL output");
+    const size_t P = (size_t)c->L.P, B = (size_t)c->cfg.batch;
+    std::vector<double> acc(B * P * 5);
+    HIPCHK(c, hipMemcpyAsync(acc.data(), c->ws + c->L.off_prof_acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const size_t plane = (size_t)c->cfg.nx * c->cfg.ny;
+    std::memset(host_out, 0, B * plane * 5 * sizeof(double));
+    for (size_t b = 0; b < B; ++b)
+        for (int k = 0; k < c->L.ncol; ++k) {
+            const size_t cell = (size_t)c->L.coly[k] * c->cfg.nx + c->L.colx[k];
+            for (int q = 0; q < 5; ++q) host_out[(b * plane + cell) * 5 + q] = acc[(b * P + k) * 5 + q];
+        }
+    return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return LBM_EINVAL;
+    *bytes = c->L.state_bytes;
+    return LBM_OK;
+}
+
+int lbm_save(lbm_ctx *c, void *dst, int64_t *step)
+{
+    CHECK_CTX(c);
+    if (!dst) return fail(c, LBM_EINVAL, "lbm_save: NULL destination");
+    HIPCHK(c, hipMemcpyAsync(dst, c->state(c->step), c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (step) *step = c->step;
+    return LBM_OK;
+}
+
+int lbm_load(lbm_ctx *c, const void *src, int64_t step)
+{
+    CHECK_CTX(c);
+    if (!src || step < 0) return fail(c, LBM_EINVAL, "lbm_load: NULL source or negative step");
+    c->step = step;
+    HIPCHK(c, hipMemcpyAsync(c->state(step), src, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_reset(lbm_ctx *c, int64_t obs_begin, int64_t obs_end)
+{
+    CHECK_CTX(c);
+    if (!c->cfg.adjoint) return fail(c, LBM_ESTATE, "adjoint buffers absent (cfg.adjoint == 0)");
+    if (obs_begin < 0 || obs_end <= obs_begin) return fail(c, LBM_EINVAL, "need 0 <= obs_begin < obs_end");
+    c->obs_begin = obs_begin;
+    c->obs_end = obs_end;
+    c->cursor = obs_end - 1;
+    c->lam_cur = 0;
+    c->adj_ready = true;
+    const size_t lam = (size_t)c->geom.pipe * c->cfg.batch * sizeof(float);
+    HIPCHK(c, launch_fill(c->ws + c->L.off_lam[0], lam, c->stream));
+    HIPCHK(c, launch_fill(c->ws + c->L.off_lam[1], lam, c->stream));
+    return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state_stride, double *grad)
+{
+    CHECK_CTX(c);
+    if (!c->cfg.adjoint || !c->adj_ready) return fail(c, LBM_ESTATE, "lbm_adjoint_step before lbm_adjoint_reset");
+    if (n < 1 || !fwd_states || (c->cfg.n_modes > 0 && !grad)) return fail(c, LBM_EINVAL, "lbm_adjoint_step: bad arguments");
+    if (c->cursor - n + 1 < 0) return fail(c, LBM_ESTATE, "lbm_adjoint_step: cursor would move below 0");
+    if (state_stride < c->L.state_bytes) return fail(c, LBM_EINVAL, "lbm_adjoint_step: state_stride < state size");
+    const int nq = 2 * c->cfg.n_modes;
+    const double wgt = 1.0 / ((double)(c->obs_end - c->obs_begin) * (double)c->L.ncol * c->cfg.nz);
+    for (int j = n - 1; j >= 0; --j) {
+        AdjointArgs a{};
+        a.state = (const char *)fwd_states + (size_t)j * state_stride;
+        a.lam_in = (const float *)(c->ws + c->L.off_lam[c->lam_cur]);
+        a.lam_out = (float *)(c->ws + c->L.off_lam[c->lam_cur ^ 1]);
+        a.grad_part = (double *)(c->ws + c->L.off_grad_part);
+        a.cursor = c->cursor;
+        a.in_window = c->cursor >= c->obs_begin && c->cursor < c->obs_end;
+        a.has_next = c->cursor + 1 < c->obs_end;
+        a.energy_weight = wgt;
+        HIPCHK(c, launch_adjoint(c->cfg.storage, c->geom, c->L.obs, a, c->stream));
+        if (nq > 0) {
+            const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
+            // the kernels use the FP32 table value of sigma; use the same rounding here
+            const double sig32 = (double)(float)sig;
+            HIPCHK(c, launch_project_grad(c->geom, c->L.obs, a.grad_part, (double *)(c->ws + c->L.off_grad_col),
+                                          (const double *)(c->ws + c->L.off_modes), nq, sig32, grad, c->stream));
+        }
+        c->lam_cur ^= 1;
+        c->cursor -= 1;
+    }
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *c)
+{
+    if (!c) return "no context";
+    return c->err.c_str();
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int p = 0; p < 2; ++p)
+        if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+}  // extern "C"

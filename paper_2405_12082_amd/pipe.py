@@ -1,0 +1,192 @@
+"""Python front end of the HIP pipe stepper (thin wrapper over include/lbm.h).
+
+PyTorch provides device memory (the workspace and output tensors) and the
+stream; every computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import LbmError, make_config
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class Pipe:
+    """One context of the library: ``batch`` pipes of one geometry on one GPU.
+
+    cfg:  dict (or keywords) with the ``lbm_config`` fields.
+    amps: [batch][2*n_modes] trigger-force amplitudes (acceleration units).
+    """
+
+    def __init__(self, cfg: dict | None = None, amps=None, device="cuda", stream=None, **kw):
+        d = dict(cfg or {})
+        d.update(kw)
+        self.cfg_dict = d
+        self.cfg = make_config(**d)
+        self.lib = _lib.lib()
+        self.layout = _lib.describe(self.cfg)
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the HIP pipe stepper needs a GPU device")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        B, nq = self.cfg.batch, 2 * self.cfg.n_modes
+        a = np.zeros((B, max(nq, 0)), np.float64)
+        if nq:
+            if amps is None:
+                raise ValueError("n_modes > 0 needs amplitudes")
+            a[:] = np.asarray(amps, np.float64).reshape(B, nq)
+        self.amps = np.ascontiguousarray(a)
+        self.workspace = torch.empty(int(self.layout.workspace_bytes), dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace is not 256-byte aligned")
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.lbm_init(C.byref(self.cfg), self.amps.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.c_void_p(_ptr(self.workspace)), C.c_size_t(self.workspace.numel()),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
+        if rc != 0:
+            raise LbmError(rc, "lbm_init failed")
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.lbm_last_error(self._ctx)
+            raise LbmError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.lbm_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.cfg.batch, self.cfg.nz, self.cfg.ny, self.cfg.nx)
+
+    @property
+    def n_fluid(self) -> int:
+        return int(self.layout.n_fluid_nodes)
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n: int = 1):
+        self._check(self.lib.lbm_step(self._ctx, int(n)), "lbm_step")
+
+    def step_graph(self, n: int, k: int = 64):
+        self._check(self.lib.lbm_step_graph(self._ctx, int(n), int(k)), "lbm_step_graph")
+
+    @property
+    def step_index(self) -> int:
+        v = C.c_int64()
+        self._check(self.lib.lbm_get_step(self._ctx, C.byref(v)), "lbm_get_step")
+        return int(v.value)
+
+    # ------------------------------------------------------------ observation
+    def moments(self):
+        B, nz, ny, nx = self.shape
+        rho = torch.empty((B, nz, ny, nx), dtype=torch.float32, device=self.device)
+        u = torch.empty((B, 3, nz, ny, nx), dtype=torch.float32, device=self.device)
+        self._check(self.lib.lbm_moments(self._ctx, C.c_void_p(_ptr(rho)), C.c_void_p(_ptr(u))), "lbm_moments")
+        return rho, u
+
+    def populations(self):
+        B, nz, ny, nx = self.shape
+        g = torch.empty((B, 27, nz, ny, nx), dtype=torch.float32, device=self.device)
+        self._check(self.lib.lbm_populations(self._ctx, C.c_void_p(_ptr(g))), "lbm_populations")
+        return g
+
+    def set_populations(self, g: torch.Tensor, step: int = 0):
+        g = g.to(device=self.device, dtype=torch.float32).contiguous()
+        if tuple(g.shape) != (self.cfg.batch, 27) + self.shape[1:]:
+            raise ValueError(f"populations must have shape {(self.cfg.batch, 27) + self.shape[1:]}")
+        self._keep = g  # alive until the stream has consumed it
+        self._check(self.lib.lbm_set_populations(self._ctx, C.c_void_p(_ptr(g)), int(step)), "lbm_set_populations")
+
+    def diagnostics(self, raise_on_nan: bool = False) -> np.ndarray:
+        out = np.zeros((self.cfg.batch, 5))
+        rc = self.lib.lbm_diagnostics(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc == _lib.LBM_ENAN and not raise_on_nan:
+            return out
+        self._check(rc, "lbm_diagnostics")
+        return out
+
+    def energy(self) -> np.ndarray:
+        out = np.zeros(self.cfg.batch)
+        self._check(self.lib.lbm_energy(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))), "lbm_energy")
+        return out
+
+    def profile_accumulate(self):
+        self._check(self.lib.lbm_profile_accumulate(self._ctx), "lbm_profile_accumulate")
+
+    def profile_reset(self):
+        self._check(self.lib.lbm_profile_reset(self._ctx), "lbm_profile_reset")
+
+    def profile_read(self) -> np.ndarray:
+        out = np.zeros((self.cfg.batch, self.cfg.ny, self.cfg.nx, 5))
+        self._check(self.lib.lbm_profile_read(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))),
+                    "lbm_profile_read")
+        return out
+
+    # ------------------------------------------------------------ checkpoints
+    @property
+    def state_bytes(self) -> int:
+        v = C.c_size_t()
+        self._check(self.lib.lbm_state_bytes(self._ctx, C.byref(v)), "lbm_state_bytes")
+        return int(v.value)
+
+    def save(self, out: torch.Tensor | None = None) -> tuple[torch.Tensor, int]:
+        if out is None:
+            out = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        step = C.c_int64()
+        self._check(self.lib.lbm_save(self._ctx, C.c_void_p(_ptr(out)), C.byref(step)), "lbm_save")
+        return out, int(step.value)
+
+    def load(self, blob: torch.Tensor, step: int):
+        self._check(self.lib.lbm_load(self._ctx, C.c_void_p(_ptr(blob)), int(step)), "lbm_load")
+
+    # ------------------------------------------------------------ adjoint
+    def adjoint_reset(self, obs_begin: int, obs_end: int):
+        self._check(self.lib.lbm_adjoint_reset(self._ctx, int(obs_begin), int(obs_end)), "lbm_adjoint_reset")
+
+    def adjoint_step(self, states: torch.Tensor, grad: torch.Tensor, n: int | None = None):
+        """Consume ``states`` ([n][state_bytes] uint8, forward order) last to first."""
+        n = states.shape[0] if n is None else n
+        stride = states.stride(0) * states.element_size()
+        self._check(self.lib.lbm_adjoint_step(self._ctx, int(n), C.c_void_p(_ptr(states)), C.c_size_t(stride),
+                                              C.c_void_p(_ptr(grad))), "lbm_adjoint_step")
+
+
+def radial_profiles(acc: np.ndarray, cfg: dict, bin_width: float = 1.0):
+    """Mean, rms, skewness and flatness of u_z per radial bin (Eq. (urmsformula),
+    pooled over time, azimuth and z) from the FP64 per-column power sums
+    returned by :meth:`Pipe.profile_read` for one pipe ([ny][nx][5])."""
+    ny, nx = acc.shape[:2]
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(xx - 0.5 * (nx - 1), yy - 0.5 * (ny - 1))
+    nb = int(np.ceil(cfg["radius"] / bin_width))
+    idx = np.minimum((r / bin_width).astype(int), nb - 1)
+    S = np.zeros((nb, 5))
+    for q in range(5):
+        S[:, q] = np.bincount(idx.ravel(), weights=acc[..., q].ravel(), minlength=nb)[:nb]
+    n = np.maximum(S[:, 4], 1.0)
+    m1, m2, m3, m4 = (S[:, q] / n for q in range(4))
+    var = np.maximum(m2 - m1 ** 2, 0.0)
+    c3 = m3 - 3 * m1 * m2 + 2 * m1 ** 3
+    c4 = m4 - 4 * m1 * m3 + 6 * m1 ** 2 * m2 - 3 * m1 ** 4
+    rms = np.sqrt(var)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        skew = np.where(var > 0, c3 / var ** 1.5, 0.0)
+        flat = np.where(var > 0, c4 / var ** 2, 0.0)
+    rc = (np.arange(nb) + 0.5) * bin_width
+    return dict(r=rc, count=S[:, 4], mean=m1, rms=rms, skewness=skew, flatness=flat)
