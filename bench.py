@@ -76,10 +76,14 @@ def main():
     ap.add_argument("--storage", type=int, default=0, help="0: FP32, 1: FP16 deviations")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run this many steps only (for profiler runs) and exit")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy a buffer of this many MiB 10 times (plain copy kernel of known "
+                         "size, to calibrate HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the stepper runs one pipe per GPU); --gpus {args.gpus} "
@@ -96,16 +100,28 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     P.lib()
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                          "launches": 10}))
+        return
     cfg = LI.preset(args.workload)
     cfg["storage"] = args.storage
     cfg["block"] = args.block
     cfg["zchunk"] = args.zchunk
+    cfg["xcd_remap"] = args.xcd_remap
     amps = LI.preset_amplitudes(cfg)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         pipe = P.Pipe(cfg, amps, stream=stream)
         if args.profile_steps:
             pipe.step(args.profile_steps)
+            pipe.stream_copy(args.profile_steps)
             torch.cuda.synchronize()
             print(json.dumps({"profile_steps": args.profile_steps, "workload": args.workload}))
             return
@@ -138,6 +154,16 @@ def main():
         ms_total = t_start.elapsed_time(t_end)
         kern_ms = [a.elapsed_time(b) for a, b in ev_pairs]
         diag = pipe.diagnostics()
+        # practical ceiling: the same access pattern as a plain 27-stream copy
+        pipe.stream_copy(5)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        n_copy = max(20, min(200, args.steps // 10))
+        c0.record(stream)
+        pipe.stream_copy(n_copy)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = c0.elapsed_time(c1) / n_copy
     finite = bool(np.all(diag[:, 4] == 0) and np.all(np.isfinite(diag[:, :4])))
     ms_step = max(ms_total, wall * 1e3) / args.steps
     mlups = nf * cfg["batch"] / (ms_step * 1e-3) / 1e6
@@ -167,7 +193,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_step", "kernel_avg_ms": round(kavg_ms, 5),
-                     "bytes_per_update": bpu, "kernel_samples": len(kern_ms)},
+                     "bytes_per_update": bpu, "kernel_samples": len(kern_ms),
+                     "copy_ceiling_gbs": round(alg_bytes / (copy_ms * 1e-3) / 1e9, 1),
+                     "frac_of_copy_ceiling": round(kavg_ms and copy_ms / kavg_ms, 4)},
         "state_finite": finite,
         "mass": float(diag[0, 0]),
     }

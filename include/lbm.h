@@ -80,6 +80,8 @@ typedef struct {
     int32_t adjoint;      /* nonzero: the workspace also holds the adjoint buffers */
     int32_t block;        /* threads per block: 64, 128, 256 (0 = default) */
     int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
+    int32_t xcd_remap;    /* workgroup -> tile order: 0 dispatch order, 1 XCD-aware (neighbouring
+                             tiles on one XCD, sharing its L2) */
 } lbm_config;
 
 /* Layout facts of a configuration (host only, no GPU needed). */
@@ -192,6 +194,13 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t n, const void *fwd_states, size_t sta
 /* Objective E(f^n) of the current forward state per pipe, FP64, host
  * [batch].  Synchronises. */
 int lbm_energy(lbm_ctx *ctx, double *host_out);
+
+/* Measurement aid: enqueue n copies of the current state buffer into the
+ * other buffer with the launch geometry of lbm_step (27 aligned loads and 27
+ * non-temporal stores per fluid node, no arithmetic): the practical HBM
+ * bandwidth ceiling of the step's access pattern.  Leaves the state
+ * unchanged (the copy goes to the spare buffer).  Async. */
+int lbm_stream_copy(lbm_ctx *ctx, int32_t n);
 
 /* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
 const char *lbm_last_error(const lbm_ctx *ctx);

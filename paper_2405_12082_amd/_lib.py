@@ -8,7 +8,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "lbm.h")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_ENAN = 0, -1, -2, -3, -4, -5
@@ -27,7 +27,7 @@ class LbmConfig(C.Structure):
         ("force_off_step", C.c_int64),
         ("storage", C.c_int32), ("wall", C.c_int32), ("pattern", C.c_int32), ("init", C.c_int32),
         ("u_tau", C.c_double),
-        ("adjoint", C.c_int32), ("block", C.c_int32), ("zchunk", C.c_int32),
+        ("adjoint", C.c_int32), ("block", C.c_int32), ("zchunk", C.c_int32), ("xcd_remap", C.c_int32),
     ]
 
 
@@ -41,7 +41,8 @@ class LbmLayout(C.Structure):
 
 CONFIG_DEFAULTS = dict(nx=24, ny=24, nz=48, batch=1, radius=10.0, tau=0.8, accel_z=0.0, n_modes=0,
                        kz=3.0, kappa=0.5, l0_frac=0.2, l_frac=0.4, period=1.0, force_off_step=0,
-                       storage=0, wall=0, pattern=0, init=0, u_tau=0.0, adjoint=0, block=0, zchunk=0)
+                       storage=0, wall=0, pattern=0, init=0, u_tau=0.0, adjoint=0, block=0, zchunk=0,
+                       xcd_remap=0)
 
 
 def make_config(**kw) -> LbmConfig:
@@ -75,6 +76,7 @@ def lib():
         "lbm_init": ([cfgp, dp, vp, C.c_size_t, vp, C.POINTER(vp)], C.c_int),
         "lbm_step": ([vp, i32], C.c_int),
         "lbm_step_graph": ([vp, i32, i32], C.c_int),
+        "lbm_stream_copy": ([vp, i32], C.c_int),
         "lbm_get_step": ([vp, C.POINTER(i64)], C.c_int),
         "lbm_moments": ([vp, fp, fp], C.c_int),
         "lbm_populations": ([vp, fp], C.c_int),

@@ -101,17 +101,18 @@ __device__ __forceinline__ void write_lambda(float *__restrict__ lam, int pstrid
 template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc;
     const int k = kb * BLOCK + threadIdx.x;
     if (k >= g.ncol) return;
     int col[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
+    const Pull<T> p = make_pull((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
+    const unsigned rowb = (unsigned)g.P * sizeof(T);
     const float *fs = g.fshape + (size_t)b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const float sig = (a.cursor >= 0 && a.cursor < g.n_sigma) ? g.sigma[a.cursor] : 0.f;
-    const T *st = (const T *)a.state + (size_t)b * g.pipe;
     const float *lin = a.lam_in + (size_t)b * g.pipe;
     float *lout = a.lam_out + (size_t)b * g.pipe;
     const float om1 = 1.f - g.omega;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, 
     for (int z = z0; z < z1; ++z) {
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
         float v[27];
-        gather<T>(st, g.pstride, g.P, col, k, z, zm, zp, v);
+        gather<T>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
         const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
         const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
         const Moments m = moments_of(v);
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, 
             Luz += we * rho * uz;
         }
         // chain rule through u = j/rho + a/2
-        const float inv = 1.f / rho;
+        const float inv = __builtin_amdgcn_rcpf(rho);
         const float Ljx = Lux * inv, Ljy = Luy * inv, Ljz = Luz * inv;
         const float Ldr = Lr - (Lux * (ux - 0.5f * ax) + Luy * (uy - 0.5f * ay) + Luz * (uz - 0.5f * az)) * inv;
         const float sx = 0.5f * rho * s.Sax + Qax + 0.5f * Lux;

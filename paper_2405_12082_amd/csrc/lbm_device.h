@@ -54,54 +54,100 @@ __host__ __device__ constexpr float H_INV_SCALE(int i)
 __host__ __device__ constexpr int NSLOT(int dx, int dy) { return (dy + 1) * 3 + (dx + 1); }
 
 // ---------------------------------------------------------------- codecs
+// Loads take a uniform (scalar) base and a 32-bit byte offset, so that the
+// compiler emits global loads with an SGPR base and one VGPR offset.  Loads
+// go through the caches (neighbouring waves share the partial lines of the
+// shifted pull reads); stores are non-temporal (written once, read next step).
 template <typename T> struct Codec;
 template <> struct Codec<float> {
-    template <int I> __device__ static __forceinline__ float load(const float *p) { return __builtin_nontemporal_load(p); }
-    template <int I> __device__ static __forceinline__ void store(float *p, float v) { __builtin_nontemporal_store(v, p); }
+    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off)
+    {
+        return *reinterpret_cast<const float *>(base + off);
+    }
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v)
+    {
+        __builtin_nontemporal_store(v, reinterpret_cast<float *>(base + off));
+    }
 };
 template <> struct Codec<__half> {
-    template <int I> __device__ static __forceinline__ float load(const __half *p)
+    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off)
     {
-        const unsigned short raw = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+        const unsigned short raw = *reinterpret_cast<const unsigned short *>(base + off);
         return __half2float(__ushort_as_half(raw)) * H_INV_SCALE(I);
     }
-    template <int I> __device__ static __forceinline__ void store(__half *p, float v)
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v)
     {
         const __half h = __float2half_rn(v * H_SCALE(I));
-        __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short *>(p));
+        __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short *>(base + off));
     }
 };
 
 // ---------------------------------------------------------------- gather
+// Per-thread view of one pipe's population buffer for one column k:
+// byte offsets of the 9 in-plane neighbour columns (own column where the
+// neighbour is solid) and a bit mask of the solid ones.
+template <typename T> struct Pull {
+    const char *base;   // pipe base
+    size_t pbytes;      // bytes between populations (nz * P * sizeof(T))
+    unsigned colo[9];   // byte offset of the column in slot d within a plane
+    unsigned wall;      // bit d set: slot d is solid
+    unsigned own;       // byte offset of column k within a plane
+};
+
+template <typename T>
+__device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k)
+{
+    Pull<T> p;
+    p.base = reinterpret_cast<const char *>(pipe);
+    p.pbytes = pstride * sizeof(T);
+    p.own = (unsigned)k * sizeof(T);
+    p.wall = 0;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        const int c = nbr[d * P + k];
+        p.colo[d] = (unsigned)(c >= 0 ? c : k) * sizeof(T);
+        if (c < 0) p.wall |= 1u << d;
+    }
+    return p;
+}
+
 // Pull streaming, Eq. (streaming): g_i(x, n) = g*_i(x - c_i, n-1) if x - c_i
 // is fluid, else the halfway bounce-back g*_opp(i)(x, n-1) (the Delta = 1/2
-// case of Eq. (fbc1)).  `col` holds the columns of the 9 in-plane offsets
-// (dx, dy) of the node (-1: solid); z - c_z wraps periodically.
+// case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
+// (periodic in z).
 template <typename T, int I>
-__device__ __forceinline__ float pull_one(const T *__restrict__ pipe, int pstride, int P, const int (&col)[9],
-                                          int k, int z, int zm, int zp)
+__device__ __forceinline__ float pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
     constexpr int d = NSLOT(-cx, -cy);
-    const int zs = cz == 0 ? z : (cz > 0 ? zm : zp);
-    const int sc = col[d];
-    if (d == 4 || sc >= 0) return Codec<T>::template load<I>(pipe + I * pstride + zs * P + sc);
-    return Codec<T>::template load<OPP(I)>(pipe + OPP(I) * pstride + z * P + k);
+    const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
+    float v = Codec<T>::template ld<I>(p.base + I * p.pbytes, zs + p.colo[d]);
+    if constexpr (d != 4) {
+        if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(I) * p.pbytes, zo + p.own);
+    }
+    return v;
 }
 
 template <typename T, int I = 0>
-__device__ __forceinline__ void gather(const T *__restrict__ pipe, int pstride, int P, const int (&col)[9], int k,
-                                       int z, int zm, int zp, float (&g)[27])
+__device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo, float (&g)[27])
 {
-    g[I] = pull_one<T, I>(pipe, pstride, P, col, k, z, zm, zp);
-    if constexpr (I + 1 < 27) gather<T, I + 1>(pipe, pstride, P, col, k, z, zm, zp, g);
+    g[I] = pull_one<T, I>(p, zo, zmo, zpo);
+    if constexpr (I + 1 < 27) gather<T, I + 1>(p, zo, zmo, zpo, g);
 }
 
 template <typename T, int I = 0>
-__device__ __forceinline__ void store_all(T *__restrict__ pipe, int pstride, int off, const float (&g)[27])
+__device__ __forceinline__ void store_all(char *pipe, size_t pbytes, unsigned off, const float (&g)[27])
 {
-    Codec<T>::template store<I>(pipe + I * pstride + off, g[I]);
-    if constexpr (I + 1 < 27) store_all<T, I + 1>(pipe, pstride, off, g);
+    Codec<T>::template st<I>(pipe + I * pbytes, off, g[I]);
+    if constexpr (I + 1 < 27) store_all<T, I + 1>(pipe, pbytes, off, g);
+}
+
+// index of the population with velocity (cx, cy, cz)
+__host__ __device__ constexpr int IDX(int cx, int cy, int cz)
+{
+    for (int i = 0; i < 27; ++i)
+        if (CX(i) == cx && CY(i) == cy && CZ(i) == cz) return i;
+    return -1;
 }
 
 // ---------------------------------------------------------------- moments
@@ -112,35 +158,34 @@ struct Moments {
     float m7, m8;       // sum (c_x^2 - c_y^2) g, (c_x^2 - c_z^2) g
 };
 
-template <int I = 0>
-__device__ __forceinline__ void accumulate_moments(const float (&g)[27], Moments &m)
+// Moments accumulated per in-plane group (c_x, c_y): with S = sum over c_z
+// of g, Zs = g(+1) - g(-1) and T = g(+1) + g(-1), every needed raw moment is
+// a signed sum of the group values.
+template <int G = 0>
+__device__ __forceinline__ void group_moments(const float (&g)[27], Moments &m)
 {
-    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    const float v = g[I];
-    m.dr += v;
-    if constexpr (cx == 1) m.jx += v;
-    if constexpr (cx == -1) m.jx -= v;
-    if constexpr (cy == 1) m.jy += v;
-    if constexpr (cy == -1) m.jy -= v;
-    if constexpr (cz == 1) m.jz += v;
-    if constexpr (cz == -1) m.jz -= v;
-    if constexpr (cx * cy == 1) m.m4 += v;
-    if constexpr (cx * cy == -1) m.m4 -= v;
-    if constexpr (cx * cz == 1) m.m5 += v;
-    if constexpr (cx * cz == -1) m.m5 -= v;
-    if constexpr (cy * cz == 1) m.m6 += v;
-    if constexpr (cy * cz == -1) m.m6 -= v;
-    if constexpr (cx * cx - cy * cy == 1) m.m7 += v;
-    if constexpr (cx * cx - cy * cy == -1) m.m7 -= v;
-    if constexpr (cx * cx - cz * cz == 1) m.m8 += v;
-    if constexpr (cx * cx - cz * cz == -1) m.m8 -= v;
-    if constexpr (I + 1 < 27) accumulate_moments<I + 1>(g, m);
+    constexpr int cx = G % 3 - 1, cy = G / 3 - 1;
+    const float g0 = g[IDX(cx, cy, 0)], gp = g[IDX(cx, cy, 1)], gm = g[IDX(cx, cy, -1)];
+    const float T = gp + gm, S = g0 + T, Zs = gp - gm;
+    m.dr += S;
+    m.jz += Zs;
+    if constexpr (cx == 1) { m.jx += S; m.m5 += Zs; }
+    if constexpr (cx == -1) { m.jx -= S; m.m5 -= Zs; }
+    if constexpr (cy == 1) { m.jy += S; m.m6 += Zs; }
+    if constexpr (cy == -1) { m.jy -= S; m.m6 -= Zs; }
+    if constexpr (cx * cy == 1) m.m4 += S;
+    if constexpr (cx * cy == -1) m.m4 -= S;
+    if constexpr (cx != 0 && cy == 0) m.m7 += S;
+    if constexpr (cx == 0 && cy != 0) m.m7 -= S;
+    if constexpr (cx != 0) m.m8 += S;
+    m.m8 -= T;
+    if constexpr (G + 1 < 9) group_moments<G + 1>(g, m);
 }
 
 __device__ __forceinline__ Moments moments_of(const float (&g)[27])
 {
     Moments m = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    accumulate_moments(g, m);
+    group_moments(g, m);
     return m;
 }
 
@@ -184,7 +229,7 @@ __device__ __forceinline__ CollideCtx collide_setup(const Moments &m, float ax, 
     CollideCtx c;
     c.dr = m.dr;
     c.rho = 1.f + m.dr;
-    const float inv = 1.f / c.rho;
+    const float inv = __builtin_amdgcn_rcpf(c.rho);
     // Eq. (macroscopic_u): u = j/rho + a/2
     ux = m.jx * inv + 0.5f * ax;
     uy = m.jy * inv + 0.5f * ay;
@@ -205,43 +250,55 @@ __device__ __forceinline__ CollideCtx collide_setup(const Moments &m, float ax, 
     return c;
 }
 
-// Post-collision deviation of population I:
-//   g*_I = (f^eq_I - w_I) + F_I/2 + sum_k c_k d_k(I)
-// f^eq - w = w (rho Pi - 1) = w ((rho-1) Pi + (Pi - 1)), Pi - 1 built without
-// cancellation; F_I = a . grad_u f^eq_I (Guo forcing in population form,
-// whose moments are the printed R^MRT); d_k = columns 4..8 of the inverse
-// moment matrix (sparse: edge links for k = 4..6, face links for 7, 8).
-template <int I>
-__device__ __forceinline__ float post_collision(const CollideCtx &c)
+// Post-collision deviations, population by population:
+//   g*_i = (f^eq_i - w_i) + F_i/2 + sum_k c_k d_k(i)
+// f^eq_i - w_i = w_i (rho Pi_i - 1) = w_i (rho (Pi_i - 1) + (rho - 1)), with
+// Pi_i - 1 = prod_a (1 + d_a) - 1 built without cancellation; F_i = a . grad_u
+// f^eq_i (Guo forcing in population form, whose moments are the printed
+// R^MRT); d_k = columns 4..8 of the inverse moment matrix (sparse: edge links
+// for k = 4..6, face links for 7, 8).  The three populations of one in-plane
+// group (c_x, c_y) share the x-y factors.
+template <int G = 0>
+__device__ __forceinline__ void group_post_collision(const CollideCtx &c, float hr, float f7, float f8, float f9,
+                                                     float (&g)[27])
 {
-    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    constexpr float w = WGT(I);
-    const float dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y), dz = dsel<cz>(c.Z);
-    const float qx = qsel<cx>(c.X), qy = qsel<cy>(c.Y), qz = qsel<cz>(c.Z);
-    const float exy = dx + dy + dx * dy;          // (1+dx)(1+dy) - 1
-    const float pim1 = exy + dz * (1.f + exy);    // Pi - 1
-    const float ez = 1.f + dz;
-    const float feq = w * (c.dr * (1.f + pim1) + pim1);
-    const float Fi = c.rho * w * (ez * (c.ax * qx * (1.f + dy) + c.ay * qy * (1.f + dx)) + c.az * qz * (1.f + exy));
-    float v = feq + 0.5f * Fi;
-    if constexpr (SHELL(I) == 1) {
-        if constexpr (cx != 0) v += (c.c7 + c.c8) * (1.f / 6.f);
-        if constexpr (cy != 0) v += c.c8 * (1.f / 6.f) - c.c7 * (1.f / 3.f);
-        if constexpr (cz != 0) v += c.c7 * (1.f / 6.f) - c.c8 * (1.f / 3.f);
+    constexpr int cx = G % 3 - 1, cy = G / 3 - 1;
+    const float dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y);
+    const float qx = qsel<cx>(c.X), qy = qsel<cy>(c.Y);
+    const float exy = fmaf(dx, dy, dx + dy);   // (1+dx)(1+dy) - 1
+    const float e1 = 1.f + exy;
+    const float A = hr * fmaf(c.ax * qx, 1.f + dy, c.ay * qy * (1.f + dx));
+    const float Bz = hr * c.az * e1;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int czr = t == 0 ? 0 : (t == 1 ? 1 : -1);
+        const float dz = czr == 0 ? c.Z.d0 : (czr > 0 ? c.Z.dp : c.Z.dm);
+        const float qz = czr == 0 ? c.Z.q0 : (czr > 0 ? c.Z.qp : c.Z.qm);
+        const float pim1 = fmaf(dz, e1, exy);
+        const float feq = fmaf(pim1, c.rho, c.dr);          // (rho Pi - 1)
+        const float fh = fmaf(qz, Bz, (1.f + dz) * A);       // F / (2 w)
+        float corr = 0.f;
+        const int shell = cx * cx + cy * cy + czr * czr;
+        if (shell == 1) corr = cx != 0 ? f7 : (cy != 0 ? f8 : f9);
+        if (shell == 2) {
+            if (czr == 0) corr = (cx * cy > 0 ? 0.25f : -0.25f) * c.c4;
+            else if (cy == 0) corr = (cx * czr > 0 ? 0.25f : -0.25f) * c.c5;
+            else corr = (cy * czr > 0 ? 0.25f : -0.25f) * c.c6;
+        }
+        const int i = t == 0 ? IDX(cx, cy, 0) : (t == 1 ? IDX(cx, cy, 1) : IDX(cx, cy, -1));
+        const float w = i == 0 ? WGT(0) : (shell == 1 ? WGT(1) : (shell == 2 ? WGT(7) : WGT(19)));
+        g[i] = fmaf(w, feq + fh, corr);
     }
-    if constexpr (SHELL(I) == 2) {
-        if constexpr (cz == 0) v += (cx * cy > 0 ? 0.25f : -0.25f) * c.c4;
-        if constexpr (cy == 0) v += (cx * cz > 0 ? 0.25f : -0.25f) * c.c5;
-        if constexpr (cx == 0) v += (cy * cz > 0 ? 0.25f : -0.25f) * c.c6;
-    }
-    return v;
+    if constexpr (G + 1 < 9) group_post_collision<G + 1>(c, hr, f7, f8, f9, g);
 }
 
-template <int I = 0>
 __device__ __forceinline__ void post_collision_all(const CollideCtx &c, float (&g)[27])
 {
-    g[I] = post_collision<I>(c);
-    if constexpr (I + 1 < 27) post_collision_all<I + 1>(c, g);
+    // face-link combinations of the relaxed stress moments 7 and 8
+    const float f7 = (c.c7 + c.c8) * (1.f / 6.f);             // +-x faces
+    const float f8 = c.c8 * (1.f / 6.f) - c.c7 * (1.f / 3.f);  // +-y faces
+    const float f9 = c.c7 * (1.f / 6.f) - c.c8 * (1.f / 3.f);  // +-z faces
+    group_post_collision(c, 0.5f * c.rho, f7, f8, f9, g);
 }
 
 // Equilibrium deviation f^eq_I(rho = 1 + dr, u) - w_I (used by the initialiser)
@@ -254,11 +311,13 @@ __device__ __forceinline__ float feq_dev(float dr, const Axis &X, const Axis &Y,
     return WGT(I) * (dr * (1.f + pim1) + pim1);
 }
 
-// Workgroup -> tile: consecutive tiles go to the same XCD (workgroups are
-// dispatched round-robin over the 8 XCDs, each with its own L2), so the
-// halo lines shared by neighbouring tiles stay in one L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+// Workgroup -> tile.  remap != 0: consecutive tiles go to the same XCD
+// (workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2), so the partial lines shared by neighbouring tiles stay in one L2;
+// remap == 0: dispatch order (spreads neighbouring tiles over the XCDs).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks, int remap)
 {
+    if (!remap) return bid;
     const int q = nblocks >> 3, r = nblocks & 7, x = bid & 7, s = bid >> 3;
     return x * q + (x < r ? x : r) + s;
 }

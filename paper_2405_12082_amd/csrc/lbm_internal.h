@@ -27,6 +27,7 @@ struct Geom {
 // tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe
 struct Tiles {
     int block, zchunk, nkb, nzc;
+    int xcd;  // nonzero: XCD-aware workgroup -> tile mapping
     long long count() const { return (long long)nkb * nzc; }
 };
 
@@ -51,6 +52,7 @@ struct ObserveArgs {
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
+hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
 hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
                           int step_off, hipStream_t s);
 hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s);

@@ -19,7 +19,7 @@ struct TileCoord {
 };
 __device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     TileCoord c;
     c.kb = tile % t.nkb;
     const int rest = tile / t.nkb;
@@ -44,35 +44,94 @@ __device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : 
 __device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
 // ---------------------------------------------------------------- step
+// Tuning knobs (compile time): LBM_PREFETCH issues the 27 loads of plane
+// z+1 before the collision of plane z; LBM_WAVES_PER_EU asks the compiler
+// for a register budget allowing that many waves per SIMD.
+#ifndef LBM_PREFETCH
+#define LBM_PREFETCH 0
+#endif
+#ifndef LBM_WAVES_PER_EU
+#define LBM_WAVES_PER_EU 0
+#endif
+#if LBM_WAVES_PER_EU > 0
+#define LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
+#else
+#define LBM_OCCUPANCY
+#endif
+
+template <typename T>
+__device__ __forceinline__ void collide_store(const Geom &g, float (&v)[27], float sig, float px, float py, float pq,
+                                              int z, char *pout, size_t pbytes, unsigned off)
+{
+    const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
+    const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
+    const Moments m = moments_of(v);
+    float ux, uy, uz;
+    const CollideCtx c = collide_setup(m, ax, ay, az, g.omega, ux, uy, uz);
+    post_collision_all(c, v);
+    store_all<T>(pout, pbytes, off, v);
+}
+
 // One time step of every fluid node: pull gather (streaming + bounce-back)
 // of g(n) from S^T g(n), collision at a(x, n), aligned store of g*(n).
 template <typename T, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
-                                                 T *__restrict__ dst, int step_off)
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
+                                                               T *__restrict__ dst, int step_off)
 {
     const TileCoord tc = decode_tile(t, BLOCK);
     const int k = tc.k;
     if (k >= g.ncol) return;
-    int col[9];
-    load_columns(g, k, col);
+    const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
     const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const long long n = *g.step_dev + step_off;
     const float sig = sigma_of(g, n);
-    const T *pin = src + (size_t)tc.b * g.pipe;
-    T *pout = dst + (size_t)tc.b * g.pipe;
+    char *pout = reinterpret_cast<char *>(dst + (size_t)tc.b * g.pipe);
+    const unsigned rowb = (unsigned)g.P * sizeof(T);
+    const int z0 = tc.zc * t.zchunk;
+    const int z1 = min(z0 + t.zchunk, g.nz);
+#if LBM_PREFETCH
+    float cur[27], nxt[27];
+    gather<T>(p, (unsigned)z0 * rowb, (unsigned)wrap_m(z0, g.nz) * rowb, (unsigned)wrap_p(z0, g.nz) * rowb, cur);
+    for (int z = z0; z < z1; ++z) {
+        const int zn = z + 1 < z1 ? z + 1 : z;  // the last plane reloads itself (cached, in bounds)
+        gather<T>(p, (unsigned)zn * rowb, (unsigned)wrap_m(zn, g.nz) * rowb, (unsigned)wrap_p(zn, g.nz) * rowb, nxt);
+        collide_store<T>(g, cur, sig, px, py, pq, z, pout, p.pbytes, (unsigned)z * rowb + p.own);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) cur[i] = nxt[i];
+    }
+#else
+    for (int z = z0; z < z1; ++z) {
+        const unsigned zo = (unsigned)z * rowb;
+        float v[27];
+        gather<T>(p, zo, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
+        collide_store<T>(g, v, sig, px, py, pq, z, pout, p.pbytes, zo + p.own);
+    }
+#endif
+}
+
+// Practical bandwidth ceiling of the step's access pattern: the same tiles,
+// 27 aligned loads and 27 non-temporal stores per fluid node, no arithmetic.
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_stream_copy(const Geom g, const Tiles t, const T *__restrict__ src,
+                                                        T *__restrict__ dst)
+{
+    const TileCoord tc = decode_tile(t, BLOCK);
+    const int k = tc.k;
+    if (k >= g.ncol) return;
+    const char *pin = reinterpret_cast<const char *>(src + (size_t)tc.b * g.pipe);
+    char *pout = reinterpret_cast<char *>(dst + (size_t)tc.b * g.pipe);
+    const size_t pbytes = (size_t)g.pstride * sizeof(T);
+    const unsigned rowb = (unsigned)g.P * sizeof(T);
     const int z0 = tc.zc * t.zchunk;
     const int z1 = min(z0 + t.zchunk, g.nz);
     for (int z = z0; z < z1; ++z) {
-        float v[27];
-        gather<T>(pin, g.pstride, g.P, col, k, z, wrap_m(z, g.nz), wrap_p(z, g.nz), v);
-        const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
-        const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
-        const Moments m = moments_of(v);
-        float ux, uy, uz;
-        const CollideCtx c = collide_setup(m, ax, ay, az, g.omega, ux, uy, uz);
-        post_collision_all(c, v);
-        store_all<T>(pout, g.pstride, z * g.P + k, v);
+        const unsigned off = (unsigned)z * rowb + (unsigned)k * sizeof(T);
+        T v[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) v[i] = *reinterpret_cast<const T *>(pin + i * pbytes + off);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) __builtin_nontemporal_store(v[i], reinterpret_cast<T *>(pout + i * pbytes + off));
     }
 }
 
@@ -116,24 +175,23 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     double psum[4] = {0, 0, 0, 0};
     int cnt = 0;
     if (active) {
-        int col[9];
-        load_columns(g, k, col);
+        const Pull<T> p = make_pull(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
         const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
         const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
         const unsigned xy = g.colxy[k];
         const int x = xy & 0xffff, y = xy >> 16;
         const size_t plane = (size_t)g.nx * g.ny;
-        const T *pin = state + (size_t)tc.b * g.pipe;
+        const unsigned rowb = (unsigned)g.P * sizeof(T);
         const int z0 = tc.zc * t.zchunk;
         const int z1 = min(z0 + t.zchunk, g.nz);
         for (int z = z0; z < z1; ++z) {
             float v[27];
-            gather<T>(pin, g.pstride, g.P, col, k, z, wrap_m(z, g.nz), wrap_p(z, g.nz), v);
+            gather<T>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
             const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
             const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
             const Moments m = moments_of(v);
             const float rho = 1.f + m.dr;
-            const float inv = 1.f / rho;
+            const float inv = __builtin_amdgcn_rcpf(rho);
             const float ux = m.jx * inv + 0.5f * ax, uy = m.jy * inv + 0.5f * ay, uz = m.jz * inv + 0.5f * az;
             const size_t node = ((size_t)tc.b * g.nz + z) * plane + (size_t)y * g.nx + x;
             if (o.flags & OBS_MOMENTS) {
@@ -259,7 +317,7 @@ __device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&c
     } else {
         v = feq_dev<OPP(J)>(0.f, zero, zero, own);
     }
-    Codec<T>::template store<J>(pipe + J * g.pstride + z * g.P + k, v);
+    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
     if constexpr (J + 1 < 27) init_slots<T, J + 1>(pipe, g, col, u0, k, z, zero, own);
 }
 
@@ -294,7 +352,7 @@ __device__ __forceinline__ void set_slots(T *pipe, const Geom &g, const int (&co
         const unsigned xy = g.colxy[k];
         v = src[OPP(J) * popstride + (size_t)z * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
     }
-    Codec<T>::template store<J>(pipe + J * g.pstride + z * g.P + k, v);
+    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
     if constexpr (J + 1 < 27) set_slots<T, J + 1>(pipe, g, col, src, k, z, plane, popstride);
 }
 
@@ -339,6 +397,17 @@ static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *d
     case 128: hipLaunchKernelGGL((k_step<T, 128>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off); break;
     default: hipLaunchKernelGGL((k_step<T, 256>), grid, dim3(256), 0, s, g, t, (const T *)src, (T *)dst, off); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
+{
+    const dim3 grid(grid_of(t, g.B));
+    if (storage == 1)
+        hipLaunchKernelGGL((k_stream_copy<unsigned short, 256>), grid, dim3(256), 0, s, g, t, (const unsigned short *)src,
+                           (unsigned short *)dst);
+    else
+        hipLaunchKernelGGL((k_stream_copy<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)src, (float *)dst);
     return hipGetLastError();
 }
 

@@ -108,8 +108,9 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.elem = c.storage == 1 ? 2 : 4;
     const long long pipe_elems = 27LL * c.nz * L.P;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
-    L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk};
-    L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk};
+    if (c.xcd_remap != 0 && c.xcd_remap != 1) return bad("xcd_remap must be 0 or 1");
+    L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap};
+    L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1};
     L.n_sigma = c.n_modes > 0 ? std::max<long long>(c.force_off_step, 0) : 0;
 
     size_t off = 0;
@@ -435,6 +436,16 @@ int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
         n -= reps * k;
     }
     return do_step_eager(c, n);
+}
+
+int lbm_stream_copy(lbm_ctx *c, int32_t n)
+{
+    CHECK_CTX(c);
+    if (n < 0) return fail(c, LBM_EINVAL, "lbm_stream_copy: n must be >= 0");
+    for (int j = 0; j < n; ++j)
+        HIPCHK(c, launch_stream_copy(c->cfg.storage, c->geom, c->L.step, c->state(c->step), c->state(c->step + 1),
+                                     c->stream));
+    return LBM_OK;
 }
 
 int lbm_get_step(const lbm_ctx *c, int64_t *step)

@@ -86,6 +86,10 @@ class Pipe:
     def step_graph(self, n: int, k: int = 64):
         self._check(self.lib.lbm_step_graph(self._ctx, int(n), int(k)), "lbm_step_graph")
 
+    def stream_copy(self, n: int = 1):
+        """n copies of the state with the step's launch geometry (bandwidth ceiling)."""
+        self._check(self.lib.lbm_stream_copy(self._ctx, int(n)), "lbm_stream_copy")
+
     @property
     def step_index(self) -> int:
         v = C.c_int64()
