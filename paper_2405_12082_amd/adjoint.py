@@ -1,0 +1,134 @@
+"""Gradient of the time-averaged streamwise kinetic energy with respect to
+the trigger-force amplitudes, by the library's discrete adjoint.
+
+Objective (time-averaged streamwise kinetic energy over a window of steps):
+    J(amps) = 1/W sum_{n=obs_begin}^{obs_end-1} (1/N_f) sum_x 1/2 rho u_z^2 (x, n)
+with the pipe started from its configured initial state and stepped
+obs_end - 1 times; the amplitudes enter through the trigger force of
+Eq. (TurbForce).
+
+Memory: forward saves a checkpoint every ``checkpoint_every`` steps; the
+reverse sweep restores one checkpoint at a time, recomputes its segment into
+a ring of saved states and runs the adjoint steps over it (checkpoint and
+recompute), so device memory is (N/C + C) states instead of N.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .pipe import Pipe
+
+
+class EnergyAdjoint:
+    """Forward runs and adjoint sweeps of J for one pipe configuration.
+
+    cfg:   configuration dict (``lbm_config`` fields); ``adjoint`` is forced on.
+    obs_begin, obs_end: the window [obs_begin, obs_end) of J.
+    """
+
+    def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
+                 device="cuda", stream=None):
+        if not (0 <= obs_begin < obs_end):
+            raise ValueError("need 0 <= obs_begin < obs_end")
+        self.cfg = dict(cfg, adjoint=1)
+        self.obs_begin, self.obs_end = int(obs_begin), int(obs_end)
+        self.C = int(checkpoint_every)
+        self.device = torch.device(device)
+        self.stream = stream
+        self.pipe = None
+        self.ckpt = None
+        self.ring = None
+        self.timing = {}
+
+    @property
+    def last_step(self) -> int:
+        return self.obs_end - 1
+
+    def _new_pipe(self, amps):
+        if self.pipe is not None:
+            self.pipe.close()
+        self.pipe = Pipe(self.cfg, amps, device=self.device, stream=self.stream)
+        return self.pipe
+
+    def objective(self, amps, keep_checkpoints: bool = False) -> np.ndarray:
+        """Run the forward model and return J per pipe ([batch] FP64)."""
+        p = self._new_pipe(amps)
+        N = self.last_step
+        if keep_checkpoints:
+            nck = N // self.C + 1
+            if self.ckpt is None or self.ckpt.shape != (nck, p.state_bytes):
+                self.ckpt = torch.empty((nck, p.state_bytes), dtype=torch.uint8, device=self.device)
+        J = np.zeros(p.cfg.batch)
+        for n in range(N + 1):
+            if keep_checkpoints and n % self.C == 0:
+                p.save(self.ckpt[n // self.C])
+            if self.obs_begin <= n:
+                J += p.energy()
+            if n < N:
+                p.step(1)
+        return J / (self.obs_end - self.obs_begin)
+
+    def forward(self, amps) -> np.ndarray:
+        """Forward run keeping checkpoints for :meth:`backward`; returns J."""
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        J = self.objective(amps, keep_checkpoints=True)
+        e1.record()
+        torch.cuda.synchronize()
+        self.timing = {"forward_ms": e0.elapsed_time(e1), "steps": self.last_step}
+        return J
+
+    def backward(self) -> np.ndarray:
+        """Reverse sweep over the last forward run: dJ/d amps [batch][2*n_modes]."""
+        p = self.pipe
+        if p is None or self.ckpt is None:
+            raise RuntimeError("backward() needs a forward() run first")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        B, nq = p.cfg.batch, 2 * p.cfg.n_modes
+        grad = torch.zeros((B, max(nq, 1)), dtype=torch.float64, device=self.device)
+        N = self.last_step
+        if self.ring is None or self.ring.shape != (self.C, p.state_bytes):
+            self.ring = torch.empty((self.C, p.state_bytes), dtype=torch.uint8, device=self.device)
+        p.adjoint_reset(self.obs_begin, self.obs_end)
+        cursor = N
+        while cursor >= 0:
+            k = cursor // self.C
+            start = k * self.C
+            p.load(self.ckpt[k], start)
+            count = cursor - start + 1
+            for j in range(count):       # recompute the segment's states
+                p.save(self.ring[j])
+                if j + 1 < count:
+                    p.step(1)
+            p.adjoint_step(self.ring[:count], grad, count)
+            cursor = start - 1
+        e1.record()
+        torch.cuda.synchronize()
+        self.timing["backward_ms"] = e0.elapsed_time(e1)
+        return grad[:, :nq].cpu().numpy()
+
+    def gradient(self, amps):
+        """J and dJ/d amps ([batch], [batch][2*n_modes])."""
+        J = self.forward(amps)
+        return J, self.backward()
+
+
+class PipeEnergy(torch.autograd.Function):
+    """J(amps) as an autograd node: forward runs the pipe (keeping
+    checkpoints), backward runs the checkpointed discrete adjoint.
+    ``amps``: [batch][2*n_modes] float64 tensor; returns J [batch]."""
+
+    @staticmethod
+    def forward(ctx, amps: torch.Tensor, runner: EnergyAdjoint):
+        J = runner.forward(amps.detach().cpu().numpy().astype(np.float64))
+        ctx.runner = runner
+        ctx.meta = (amps.dtype, amps.device)
+        return torch.as_tensor(J, dtype=amps.dtype, device=amps.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        dtype, device = ctx.meta
+        g = torch.as_tensor(ctx.runner.backward(), dtype=dtype, device=device)
+        return gJ.reshape(-1, 1) * g, None

@@ -1,0 +1,103 @@
+"""GPU discrete adjoint against the FP64 oracle adjoint and against central
+finite differences of the GPU forward model (needs an MI355X).
+
+Tolerances: the GPU gradient (FP32 forward and adjoint states, FP64
+gradient accumulation) agrees with the oracle's FP64 adjoint to 1e-4
+relative (max norm over the amplitudes) on a tiny pipe, and with central
+finite differences of its own forward model to 1e-4 relative (2-norm).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import lbm_inputs as LI
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_12082_amd as P
+    from paper_2405_12082_amd import adjoint
+    P.lib()
+    return adjoint
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+TINY = dict(nx=12, ny=12, nz=8, batch=1, radius=5.0, tau=0.6, accel_z=1e-5, n_modes=2, kz=1.0, kappa=0.5,
+            l0_frac=0.2, l_frac=0.4, period=20.0, force_off_step=1000, init=1, u_tau=0.01)
+TINY_AMPS = np.array([1e-4, 2e-4, 3e-4, 1.5e-4])
+
+
+def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod):
+    O = oracle_mod
+    run = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=7)
+    J, g = run.gradient(TINY_AMPS[None])
+    Jo, go = O.adjoint_gradient(O.make_config(**TINY), TINY_AMPS, 20, 40)
+    err = np.abs(g[0] - go).max() / np.abs(go).max()
+    _log(f"J gpu {J[0]:.10e} oracle {Jo:.10e}; gradient error vs oracle adjoint {err:.3e}")
+    assert abs(J[0] - Jo) < 1e-5 * abs(Jo)  # FP32 state: u_z to ~1e-6 relative
+    assert err < 1e-4
+
+
+def test_checkpoint_interval_does_not_change_the_gradient(gpu):
+    g1 = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=7).gradient(TINY_AMPS[None])[1]
+    g2 = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=40).gradient(TINY_AMPS[None])[1]
+    assert np.array_equal(g1, g2)
+
+
+def test_batched_adjoint_equals_single_pipes(gpu):
+    cfg = dict(TINY, batch=3)
+    amps = np.stack([TINY_AMPS, 0.5 * TINY_AMPS, TINY_AMPS[::-1].copy()])
+    Jb, gb = gpu.EnergyAdjoint(cfg, 20, 40, checkpoint_every=10).gradient(amps)
+    for b in range(3):
+        J1, g1 = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=10).gradient(amps[b:b + 1])
+        assert J1[0] == Jb[b]
+        assert np.array_equal(g1[0], gb[b])
+
+
+def test_autograd_function(gpu):
+    run = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=9)
+    amps = torch.tensor(TINY_AMPS[None], dtype=torch.float64, requires_grad=True)
+    J = gpu.PipeEnergy.apply(amps, run)
+    (3.0 * J.sum()).backward()
+    _, g = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=9).gradient(TINY_AMPS[None])
+    np.testing.assert_allclose(amps.grad.numpy(), 3.0 * g, rtol=0, atol=0)
+
+
+def _fd_config():
+    # a small pipe in the shape of the adjoint workload (nu = 0.0032, trigger
+    # force active throughout, log-law start)
+    cfg = LI.preset("adjoint")
+    cfg.update(nx=32, ny=32, nz=96, radius=15.0)
+    cfg["period"] = float(round(0.052 * 15.0 / cfg["u_tau"]))
+    return cfg
+
+
+def test_adjoint_matches_central_differences(gpu):
+    cfg = _fd_config()
+    b, e = 150, 300
+    amps = LI.preset_amplitudes(cfg) * 20.0
+    run = gpu.EnergyAdjoint(cfg, b, e, checkpoint_every=50)
+    J, g = run.gradient(amps)
+    g = g[0]
+    rel = {}
+    for frac in (1e-1, 3e-2):
+        fd = np.zeros_like(g)
+        for q in range(g.size):
+            eps = frac * np.abs(amps).max()
+            ap, am = amps.copy(), amps.copy()
+            ap[0, q] += eps
+            am[0, q] -= eps
+            fd[q] = (run.objective(ap)[0] - run.objective(am)[0]) / (2 * eps)
+        rel[frac] = np.linalg.norm(g - fd) / np.linalg.norm(fd)
+        _log(f"eps = {frac:g} * max|amps|: |g - g_fd| / |g_fd| = {rel[frac]:.3e}")
+    assert min(rel.values()) < 1e-4
