@@ -67,6 +67,126 @@ def cpu_baseline(cfg, amps, seconds=12.0):
                       f"{steps} steps, {nf} fluid nodes, {dt:.1f} s"}
 
 
+def _events(stream):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    return a, b
+
+
+def leg_fp16(steps=500):
+    """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    cfg = LI.preset("turbulent")
+    cfg["storage"] = 1
+    amps = LI.preset_amplitudes(cfg)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = P.Pipe(cfg, amps, stream=stream)
+        p.step(20)
+        a, b = _events(stream)
+        a.record(stream)
+        p.step(steps)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        ok = bool(p.diagnostics()[0, 4] == 0)
+    nf = p.n_fluid
+    bpu = int(p.layout.bytes_per_update)
+    del p
+    torch.cuda.empty_cache()
+    gbs = nf * bpu / (ms * 1e-3) / 1e9
+    return {"value": round(nf / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 4),
+            "bytes_per_update": bpu, "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "steps": steps, "state_finite": ok}
+
+
+def leg_batched(steps=200, graph_k=50):
+    """64 independent pipes 64x64x256 (R = 30) with their own seeded forcing:
+    one context, autotuned launch geometry and step order, graph replay;
+    against the same pipes run one after another as single-pipe contexts."""
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    from paper_2405_12082_amd import autotune
+    cfg = LI.preset("batched")
+    amps = LI.preset_amplitudes(cfg)
+    B = cfg["batch"]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = P.Pipe(cfg, amps, stream=stream)
+        tune = autotune.autotune(p, steps=10)
+        p.step_graph(2 * graph_k, graph_k)  # capture + warm
+        a, b = _events(stream)
+        a.record(stream)
+        p.step_graph(steps, graph_k)
+        b.record(stream)
+        b.synchronize()
+        ms_batched = a.elapsed_time(b) / steps
+        nf = p.n_fluid
+        ok = bool((p.diagnostics()[:, 4] == 0).all())
+        del p
+        torch.cuda.empty_cache()
+        # sequential single-pipe launches (eager, default geometry)
+        c1 = dict(cfg, batch=1)
+        singles = [P.Pipe(c1, amps[i:i + 1], stream=stream) for i in range(B)]
+        for q in singles:
+            q.step(2)
+        a, b = _events(stream)
+        a.record(stream)
+        for q in singles:
+            q.step(steps)
+        b.record(stream)
+        b.synchronize()
+        ms_seq = a.elapsed_time(b) / steps
+        del singles
+        torch.cuda.empty_cache()
+    return {"value": round(B * nf / (ms_batched * 1e-3) / 1e6, 1), "unit": "MLUPS (aggregate)",
+            "ms_per_step": round(ms_batched, 4), "pipes": B, "fluid_nodes_per_pipe": nf,
+            "launch": tune["best"], "graph_steps": graph_k, "autotune_cached": tune["cached"],
+            "sequential_single_pipes": {"value": round(B * nf / (ms_seq * 1e-3) / 1e6, 1),
+                                        "ms_per_step": round(ms_seq, 4)},
+            "speedup_vs_sequential": round(ms_seq / ms_batched, 3), "state_finite": ok}
+
+
+def leg_adjoint():
+    """Adjoint workload: 96x96x384 pipe (R = 45), 2000 steps, checkpoints
+    every 100; gradient of the streamwise energy over steps 1501..2000 with
+    respect to the 12 trigger amplitudes.  Cost ratio = (recompute + adjoint
+    sweep) / plain forward over the same steps."""
+    import numpy as np
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    from paper_2405_12082_amd.adjoint import EnergyAdjoint
+    cfg = LI.preset("adjoint")
+    amps = LI.preset_amplitudes(cfg)
+    N = cfg["obs_end"] - 1
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = P.Pipe(cfg, amps, stream=stream)
+        a, b = _events(stream)
+        a.record(stream)
+        p.step(N)
+        b.record(stream)
+        b.synchronize()
+        ms_fwd = a.elapsed_time(b)
+        nf = p.n_fluid
+        del p
+        run = EnergyAdjoint(cfg, cfg["obs_begin"], cfg["obs_end"], checkpoint_every=cfg["checkpoint_every"],
+                            stream=stream)
+        J, g = run.gradient(amps)
+        t = dict(run.timing)
+        del run
+        torch.cuda.empty_cache()
+    return {"steps": N, "forward_plain_ms": round(ms_fwd, 2),
+            "forward_with_checkpoints_ms": round(t["forward_ms"], 2), "backward_ms": round(t["backward_ms"], 2),
+            "adjoint_fwd_cost_ratio": round(t["backward_ms"] / ms_fwd, 3),
+            "J": float(J[0]), "grad_norm": float(np.linalg.norm(g[0])),
+            "fluid_nodes": nf, "checkpoint_every": cfg["checkpoint_every"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +198,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="fp16,batched,adjoint",
+                    help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run this many steps only (for profiler runs) and exit")
@@ -199,6 +321,14 @@ def main():
         "state_finite": finite,
         "mass": float(diag[0, 0]),
     }
+    del pipe
+    torch.cuda.empty_cache()
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    extra = {}
+    for leg in legs:
+        extra[leg] = {"fp16": leg_fp16, "batched": leg_batched, "adjoint": leg_adjoint}[leg]()
+    if extra:
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         c1 = dict(cfg)
         out["cpu_baseline"] = cpu_baseline(c1, amps[0], args.cpu_seconds)

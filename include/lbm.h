@@ -126,6 +126,19 @@ int lbm_step(lbm_ctx *ctx, int32_t n);
  * launches for the remainder.  Async.  Same results as lbm_step. */
 int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
 
+/* Change the launch geometry of lbm_step and lbm_step_graph on a live
+ * context: threads per block (64, 128, 256), z planes per thread (1..64),
+ * tile order (xcd_remap 0 or 1), pipes per launch (1..batch) and step order
+ * (pipe_major 0: every step covers all pipes; 1: within one call, each group
+ * of pipes_per_launch pipes runs all n steps before the next group, so a
+ * small pipe's working set stays in the 256 MB Infinity Cache).  A value of
+ * 0 (-1 for xcd_remap and pipe_major) keeps the current setting.  Drops
+ * captured graphs.  Results do not depend on the geometry (the pipes are
+ * independent and every node's update is the same arithmetic).
+ * Errors: LBM_EINVAL for values out of range. */
+int lbm_set_launch(lbm_ctx *ctx, int32_t block, int32_t zchunk, int32_t xcd_remap, int32_t pipes_per_launch,
+                   int32_t pipe_major);
+
 /* Current step index n (the state held is f^n, before its collision). */
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 

@@ -1,0 +1,85 @@
+"""Launch-geometry autotuner for the fused step.
+
+Exhaustive search over (threads per block, z planes per thread, tile order,
+pipes per launch) on a live context: each candidate is set with
+``lbm_set_launch`` and timed over a few steps with HIP events on the pipe's
+stream.  The state is saved before and restored after the search, so tuning
+does not advance the simulation.  Results are cached in a JSON file keyed by
+the pipe shape, batch, storage and GPU architecture.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import torch
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_mi355x", "autotune.json")
+
+
+def _key(pipe) -> str:
+    c = pipe.cfg
+    arch = torch.cuda.get_device_properties(pipe.device).gcnArchName.split(":")[0]
+    return f"{arch}|{c.nx}x{c.ny}x{c.nz}|R{c.radius:g}|B{c.batch}|s{c.storage}"
+
+
+def candidates(batch: int):
+    ppl = sorted({batch, max(1, batch // 2), max(1, batch // 4), max(1, batch // 8), 1}, reverse=True)
+    orders = (0, 1) if batch > 1 else (0,)
+    for block, zchunk, xcd, p, pm in itertools.product((64, 128, 256), (1, 2, 4, 8, 16), (0, 1), ppl, orders):
+        if pm == 1 and p == batch:
+            continue  # one group: both orders are the same launch sequence
+        yield dict(block=block, zchunk=zchunk, xcd_remap=xcd, pipes_per_launch=p, pipe_major=pm)
+
+
+def _time(pipe, steps: int) -> float:
+    stream = pipe.stream
+    pipe.step(2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pipe.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def autotune(pipe, steps: int = 10, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+             verbose: bool = False) -> dict:
+    """Pick the fastest launch geometry for ``pipe`` and apply it.
+
+    Returns {"best": {...}, "ms_per_step": t, "tried": n, "cached": bool}."""
+    key = _key(pipe)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if not force and key in cache:
+        best = cache[key]["best"]
+        pipe.set_launch(**best)
+        return dict(cache[key], cached=True)
+    blob, step0 = pipe.save()
+    blob = blob.clone()
+    results = []
+    for cand in candidates(pipe.cfg.batch):
+        pipe.set_launch(**cand)
+        ms = _time(pipe, steps)
+        results.append((ms, cand))
+        if verbose:
+            print(f"autotune {cand} {ms:.4f} ms/step", flush=True)
+    pipe.load(blob, step0)
+    torch.cuda.synchronize()
+    ms, best = min(results, key=lambda r: r[0])
+    pipe.set_launch(**best)
+    rec = {"best": best, "ms_per_step": ms, "tried": len(results)}
+    if cache_path:
+        cache[key] = rec
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return dict(rec, cached=False)

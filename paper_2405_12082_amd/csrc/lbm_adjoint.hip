@@ -102,7 +102,7 @@ template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
-    const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc;
+    const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc + t.b0;
     const int k = kb * BLOCK + threadIdx.x;
     if (k >= g.ncol) return;
     int col[9];
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ cols
 
 hipError_t launch_adjoint(int storage, const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)(t.count() * g.B));
+    const dim3 grid((unsigned)(t.count() * t.nb));
     if (storage == 1)
         hipLaunchKernelGGL((k_adjoint<__half, 256>), grid, dim3(256), 0, s, g, t, a);
     else

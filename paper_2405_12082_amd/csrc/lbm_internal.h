@@ -28,6 +28,8 @@ struct Geom {
 struct Tiles {
     int block, zchunk, nkb, nzc;
     int xcd;  // nonzero: XCD-aware workgroup -> tile mapping
+    int b0;   // first pipe of the launch
+    int nb;   // pipes covered by the launch
     long long count() const { return (long long)nkb * nzc; }
 };
 

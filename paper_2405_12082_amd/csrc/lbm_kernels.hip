@@ -24,7 +24,7 @@ __device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
     c.kb = tile % t.nkb;
     const int rest = tile / t.nkb;
     c.zc = rest % t.nzc;
-    c.b = rest / t.nzc;
+    c.b = rest / t.nzc + t.b0;
     c.k = c.kb * block + threadIdx.x;
     return c;
 }
@@ -386,12 +386,12 @@ __global__ void k_set_step(long long *p, long long v, int add)
 }
 
 // ---------------------------------------------------------------- launchers
-static int grid_of(const Tiles &t, int B) { return (int)(t.count() * B); }
+static int grid_of(const Tiles &t) { return (int)(t.count() * t.nb); }
 
 template <typename T>
 static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
 {
-    const dim3 grid(grid_of(t, g.B));
+    const dim3 grid(grid_of(t));
     switch (t.block) {
     case 64: hipLaunchKernelGGL((k_step<T, 64>), grid, dim3(64), 0, s, g, t, (const T *)src, (T *)dst, off); break;
     case 128: hipLaunchKernelGGL((k_step<T, 128>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off); break;
@@ -402,7 +402,7 @@ static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *d
 
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
 {
-    const dim3 grid(grid_of(t, g.B));
+    const dim3 grid(grid_of(t));
     if (storage == 1)
         hipLaunchKernelGGL((k_stream_copy<unsigned short, 256>), grid, dim3(256), 0, s, g, t, (const unsigned short *)src,
                            (unsigned short *)dst);
@@ -419,7 +419,7 @@ hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *s
 hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off,
                           hipStream_t s)
 {
-    const dim3 grid(grid_of(t, g.B));
+    const dim3 grid(grid_of(t));
     if (storage == 1)
         hipLaunchKernelGGL((k_observe<__half, 256>), grid, dim3(256), 0, s, g, t, (const __half *)state, o, off);
     else

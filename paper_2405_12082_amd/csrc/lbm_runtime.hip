@@ -109,8 +109,8 @@ int build_layout(const lbm_config *cfg, Layout &L)
     const long long pipe_elems = 27LL * c.nz * L.P;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return bad("xcd_remap must be 0 or 1");
-    L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap};
-    L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1};
+    L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap, 0, c.batch};
+    L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1, 0, c.batch};
     L.n_sigma = c.n_modes > 0 ? std::max<long long>(c.force_off_step, 0) : 0;
 
     size_t off = 0;
@@ -191,6 +191,8 @@ struct lbm_ctx {
     int sticky = 0;
     std::string err;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int ppl = 1;         // pipes per step launch
+    int pipe_major = 0;  // 1: each pipe group runs all steps of a call before the next group
     int graph_k[2] = {0, 0};
     // adjoint
     bool adj_ready = false;
@@ -225,11 +227,31 @@ int fail(lbm_ctx *c, int code, const std::string &msg)
         if ((ctx)->sticky) return LBM_EHIP;                                                                 \
     } while (0)
 
+// n steps from step index `first` (state buffer parity) for every pipe,
+// one launch per group of pipes_per_launch pipes, step-major or pipe-major
+hipError_t launch_steps(lbm_ctx *c, long long first, int n, hipStream_t s)
+{
+    const int B = c->cfg.batch;
+    auto one = [&](int b0, int j) {
+        Tiles t = c->L.step;
+        t.b0 = b0;
+        t.nb = std::min(c->ppl, B - b0);
+        return launch_step(c->cfg.storage, c->geom, t, c->state(first + j), c->state(first + j + 1), j, s);
+    };
+    hipError_t e = hipSuccess;
+    if (c->pipe_major) {
+        for (int b0 = 0; b0 < B && e == hipSuccess; b0 += c->ppl)
+            for (int j = 0; j < n && e == hipSuccess; ++j) e = one(b0, j);
+    } else {
+        for (int j = 0; j < n && e == hipSuccess; ++j)
+            for (int b0 = 0; b0 < B && e == hipSuccess; b0 += c->ppl) e = one(b0, j);
+    }
+    return e;
+}
+
 int do_step_eager(lbm_ctx *c, int n)
 {
-    for (int j = 0; j < n; ++j)
-        HIPCHK(c, launch_step(c->cfg.storage, c->geom, c->L.step, c->state(c->step + j), c->state(c->step + j + 1), j,
-                              c->stream));
+    HIPCHK(c, launch_steps(c, c->step, n, c->stream));
     if (n > 0) HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
     c->step += n;
     return LBM_OK;
@@ -286,6 +308,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     if (!workspace || bytes < c->L.total || ((uintptr_t)workspace & 255)) return bail(LBM_ENOMEM);
     if (cfg->n_modes > 0 && !amps) return bail(LBM_EINVAL);
     c->cfg = *cfg;
+    c->ppl = cfg->batch;
     if (!c->cfg.block) c->cfg.block = kDefaultBlock;
     if (!c->cfg.zchunk) c->cfg.zchunk = kDefaultZChunk;
     c->stream = (hipStream_t)stream;
@@ -413,9 +436,7 @@ int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
             hipGraph_t gr = nullptr;
             HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
-            for (int j = 0; j < k && e == hipSuccess; ++j)
-                e = launch_step(c->cfg.storage, c->geom, c->L.step, c->state(c->step + j), c->state(c->step + j + 1), j,
-                                c->cap_stream);
+            e = launch_steps(c, c->step, k, c->cap_stream);
             if (e == hipSuccess) e = launch_set_step(const_cast<long long *>(c->geom.step_dev), k, 1, c->cap_stream);
             const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
             if (e != hipSuccess || e2 != hipSuccess) {
@@ -436,6 +457,40 @@ int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
         n -= reps * k;
     }
     return do_step_eager(c, n);
+}
+
+int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap, int32_t ppl, int32_t pipe_major)
+{
+    CHECK_CTX(c);
+    if (pipe_major < -1 || pipe_major > 1) return fail(c, LBM_EINVAL, "pipe_major must be -1, 0 or 1");
+    if (block && block != 64 && block != 128 && block != 256) return fail(c, LBM_EINVAL, "block must be 64, 128 or 256");
+    if (zchunk && (zchunk < 1 || zchunk > 64)) return fail(c, LBM_EINVAL, "zchunk must be in 1..64");
+    if (xcd_remap < -1 || xcd_remap > 1) return fail(c, LBM_EINVAL, "xcd_remap must be -1, 0 or 1");
+    if (ppl < 0 || ppl > c->cfg.batch) return fail(c, LBM_EINVAL, "pipes_per_launch must be in 0..batch");
+    Tiles &t = c->L.step;
+    if (block) {
+        t.block = block;
+        t.nkb = (c->L.ncol + block - 1) / block;
+        c->cfg.block = block;
+    }
+    if (zchunk) {
+        t.zchunk = zchunk;
+        t.nzc = (c->cfg.nz + zchunk - 1) / zchunk;
+        c->cfg.zchunk = zchunk;
+    }
+    if (xcd_remap >= 0) {
+        t.xcd = xcd_remap;
+        c->cfg.xcd_remap = xcd_remap;
+    }
+    if (ppl) c->ppl = ppl;
+    if (pipe_major >= 0) c->pipe_major = pipe_major;
+    for (int p = 0; p < 2; ++p)
+        if (c->graph[p]) {
+            (void)hipGraphExecDestroy(c->graph[p]);
+            c->graph[p] = nullptr;
+            c->graph_k[p] = 0;
+        }
+    return LBM_OK;
 }
 
 int lbm_stream_copy(lbm_ctx *c, int32_t n)

@@ -86,6 +86,12 @@ class Pipe:
     def step_graph(self, n: int, k: int = 64):
         self._check(self.lib.lbm_step_graph(self._ctx, int(n), int(k)), "lbm_step_graph")
 
+    def set_launch(self, block: int = 0, zchunk: int = 0, xcd_remap: int = -1, pipes_per_launch: int = 0,
+                   pipe_major: int = -1):
+        """Change the step's launch geometry and order (0 / -1 keep the current value)."""
+        self._check(self.lib.lbm_set_launch(self._ctx, int(block), int(zchunk), int(xcd_remap),
+                                            int(pipes_per_launch), int(pipe_major)), "lbm_set_launch")
+
     def stream_copy(self, n: int = 1):
         """n copies of the state with the step's launch geometry (bandwidth ceiling)."""
         self._check(self.lib.lbm_stream_copy(self._ctx, int(n)), "lbm_stream_copy")
