@@ -72,12 +72,15 @@ typedef struct {
     double l_frac;        /* l / R */
     double period;        /* forcing period T in steps: time factor sin(2 pi n / T) */
     int64_t force_off_step; /* trigger force applied for steps n < force_off_step */
-    int32_t storage;      /* 0: FP32 deviations; 1: FP16 deviations scaled by 2^k ~ 1/w_i */
+    int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations scaled by
+                             2^k ~ 1/w_i, FP32 collision; 2: FP64 deviations and collision
+                             (reference precision, for verification) */
     int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1)) */
     int32_t pattern;      /* 0: two buffers (A/B) */
     int32_t init;         /* 0: rest (g = 0); 1: log-law mean profile, f = f^eq(1, u_z(r)) */
     double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
-    int32_t adjoint;      /* nonzero: the workspace also holds the adjoint buffers */
+    int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state and
+                             arithmetic, 2 FP64 adjoint state and arithmetic */
     int32_t block;        /* threads per block: 64, 128, 256 (0 = default) */
     int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
     int32_t xcd_remap;    /* workgroup -> tile order: 0 dispatch order, 1 XCD-aware (neighbouring
@@ -180,13 +183,13 @@ int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 int lbm_save(lbm_ctx *ctx, void *dst, int64_t *step);
 int lbm_load(lbm_ctx *ctx, const void *src, int64_t step);
 
-/* Discrete adjoint of lbm_step (requires cfg.adjoint != 0).
+/* Discrete adjoint of lbm_step (requires cfg.adjoint = 1 or 2).
  * Forward map of one step: f^{n+1} = S C(f^n, a^n), C the collision at every
  * fluid node, S the streaming with the wall.  Objective:
  *     J = 1/W sum_{n in [obs_begin, obs_end)} E(f^n),
  *     E(f^n) = (1/N_f) sum_x 1/2 rho u_z^2 with u_z = j_z/rho + a_z(x, n)/2,
  * the time-averaged streamwise kinetic energy, W = obs_end - obs_begin.
- * The adjoint state lambda^n = dJ/df^n lives in the workspace (FP32):
+ * The adjoint state lambda^n = dJ/df^n lives in the workspace (FP32 or FP64):
  *     lambda^c = (dC/df^c)^T S^T lambda^{c+1} + dE_c/df^c [c in window],
  * with lambda^{N+1} = 0 for the last state N = obs_end - 1.
  *
@@ -207,6 +210,17 @@ int lbm_adjoint_step(lbm_ctx *ctx, int32_t n, const void *fwd_states, size_t sta
 /* Objective E(f^n) of the current forward state per pipe, FP64, host
  * [batch].  Synchronises. */
 int lbm_energy(lbm_ctx *ctx, double *host_out);
+/* Same value added to a device accumulator: acc[b] += E_b(f^n) (device
+ * [batch] doubles, caller-owned), fixed-order FP64 reduction.  Async. */
+int lbm_energy_accumulate(lbm_ctx *ctx, double *acc);
+
+/* Record forward states for checkpoint-and-recompute without touching the
+ * context's own state: ring[0] := start (a saved state, lbm_save layout, of
+ * step s0; no copy when start == ring), then ring[j+1] := one step of
+ * ring[j] at step index s0 + j, for j = 0 .. n-2.  ring: device memory for
+ * n states, stride bytes apart (stride >= lbm_state_bytes, multiple of 256).
+ * The states are exactly those lbm_step would produce.  Async. */
+int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *ring, size_t stride);
 
 /* Measurement aid: enqueue n copies of the current state buffer into the
  * other buffer with the launch geometry of lbm_step (27 aligned loads and 27

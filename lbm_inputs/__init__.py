@@ -106,6 +106,32 @@ def random_deviations(seed: int, shape, amp: float = 0.02) -> np.ndarray:
     return (amp * sc * (2.0 * u - 1.0)).astype(np.float32)
 
 
+def random_deviations_torch(seed: int, shape, amp: float = 0.02, device="cuda"):
+    """Same values as :func:`random_deviations`, generated on the device one
+    direction at a time (for full-size fields): float32 tensor [27][...]."""
+    import torch
+    n = int(np.prod(shape))
+    out = torch.empty((27,) + tuple(shape), dtype=torch.float32, device=device)
+    for i in range(27):
+        idx = torch.arange(i * n, (i + 1) * n, dtype=torch.int64, device=device)
+        u = hash_uniform_torch(seed, idx)
+        del idx
+        sc = float(amp * deviation_scale(i))
+        out[i] = (sc * (2.0 * u - 1.0)).to(torch.float32).reshape(shape)
+        del u
+    return out
+
+
+def random_deviations_at(seed: int, shape, i, idx_rest, amp: float = 0.02) -> np.ndarray:
+    """Entries of :func:`random_deviations` at direction(s) i and flat index
+    idx_rest within ``shape`` (vectorised, float32)."""
+    n = int(np.prod(shape))
+    i = np.asarray(i)
+    flat = i.astype(np.uint64) * np.uint64(n) + np.asarray(idx_rest, dtype=np.uint64)
+    u = hash_uniform(seed, flat)
+    return (amp * deviation_scale(i) * (2.0 * u - 1.0)).astype(np.float32)
+
+
 def amplitude_unit(u_tau: float, period: float) -> float:
     """Acceleration per unit dimensionless amplitude: u_b * pi / T.
 

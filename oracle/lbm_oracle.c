@@ -285,6 +285,18 @@ static double time_factor(const orc_config *c, int64_t n)
     return sin(2.0 * M_PI * (double)n / c->period);
 }
 
+/* body acceleration a(x, n) at node (x, y, z), step n: h z^ + time factor x trigger shape */
+void orc_force_at(const orc_config *c, const double *amps, int32_t x, int32_t y, int32_t z, int64_t n,
+                  double out[3])
+{
+    double s[3];
+    orc_trigger_shape(c, amps, x, y, z, s);
+    const double tf = time_factor(c, n);
+    out[0] = tf * s[0];
+    out[1] = tf * s[1];
+    out[2] = c->accel_z + tf * s[2];
+}
+
 /* ---------------------------------------------------------------------- */
 /* pipe state                                                              */
 /* ---------------------------------------------------------------------- */

@@ -58,6 +58,11 @@ double orc_bouzidi(double delta, double fs_out_x, double fs_in_x, double fs_out_
 void orc_trigger_shape(const orc_config *cfg, const double *amps, double x, double y, double z,
                        double out[3]);
 
+/* Body acceleration a(x, n) = h z^ + sin(2 pi n / T) [n < force_off_step] x
+ * trigger shape, at node (x, y, z) and step n. */
+void orc_force_at(const orc_config *cfg, const double *amps, int32_t x, int32_t y, int32_t z, int64_t n,
+                  double out[3]);
+
 /* --- pipe stepper --- */
 orc_pipe *orc_pipe_new(const orc_config *cfg, const double *amps /* [2*n_modes] or NULL */);
 void orc_pipe_free(orc_pipe *p);

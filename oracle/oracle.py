@@ -65,6 +65,7 @@ def lib():
         L.orc_bouzidi.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32]
         L.orc_bouzidi.restype = C.c_double
         L.orc_trigger_shape.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_force_at.argtypes = [cfgp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp]
         L.orc_pipe_new.argtypes = [cfgp, dp]
         L.orc_pipe_new.restype = C.c_void_p
         L.orc_pipe_free.argtypes = [C.c_void_p]
@@ -189,6 +190,17 @@ def trigger_shape(cfg: OrcConfig, amps, x, y, z):
     amps = _f64(np.resize(np.asarray(amps, float), 12) if len(amps) else np.zeros(12))
     out = np.zeros(3)
     lib().orc_trigger_shape(C.byref(cfg), _p(amps), float(x), float(y), float(z), _p(out))
+    return out
+
+
+def force_at(cfg: OrcConfig, amps, x, y, z, n):
+    """Body acceleration a(x, n) at node (x, y, z) and step n."""
+    a = np.zeros(12)
+    k = 2 * max(cfg.n_modes, 0)
+    if k:
+        a[:k] = np.asarray(amps, float)[:k]
+    out = np.zeros(3)
+    lib().orc_force_at(C.byref(cfg), _p(a), int(x), int(y), int(z), int(n), _p(out))
     return out
 
 

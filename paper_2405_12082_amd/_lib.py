@@ -92,6 +92,8 @@ def lib():
         "lbm_adjoint_reset": ([vp, i64, i64], C.c_int),
         "lbm_adjoint_step": ([vp, i32, vp, C.c_size_t, vp], C.c_int),
         "lbm_energy": ([vp, dp], C.c_int),
+        "lbm_energy_accumulate": ([vp, vp], C.c_int),
+        "lbm_recompute": ([vp, vp, i64, i32, vp, C.c_size_t], C.c_int),
         "lbm_last_error": ([vp], C.c_char_p),
         "lbm_destroy": ([vp], None),
     }

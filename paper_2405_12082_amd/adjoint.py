@@ -23,15 +23,19 @@ from .pipe import Pipe
 class EnergyAdjoint:
     """Forward runs and adjoint sweeps of J for one pipe configuration.
 
-    cfg:   configuration dict (``lbm_config`` fields); ``adjoint`` is forced on.
+    cfg:   configuration dict (``lbm_config`` fields).
     obs_begin, obs_end: the window [obs_begin, obs_end) of J.
+    precision: "fp64" (adjoint state and vector-Jacobian arithmetic in FP64)
+    or "fp32"; the forward model is the same FP32-arithmetic stepper.
     """
 
     def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, precision: str = "fp64"):
         if not (0 <= obs_begin < obs_end):
             raise ValueError("need 0 <= obs_begin < obs_end")
-        self.cfg = dict(cfg, adjoint=1)
+        if precision not in ("fp32", "fp64"):
+            raise ValueError("precision must be 'fp32' or 'fp64'")
+        self.cfg = dict(cfg, adjoint=2 if precision == "fp64" else 1)
         self.obs_begin, self.obs_end = int(obs_begin), int(obs_end)
         self.C = int(checkpoint_every)
         self.device = torch.device(device)
@@ -59,15 +63,15 @@ class EnergyAdjoint:
             nck = N // self.C + 1
             if self.ckpt is None or self.ckpt.shape != (nck, p.state_bytes):
                 self.ckpt = torch.empty((nck, p.state_bytes), dtype=torch.uint8, device=self.device)
-        J = np.zeros(p.cfg.batch)
+        acc = torch.zeros(p.cfg.batch, dtype=torch.float64, device=self.device)
         for n in range(N + 1):
             if keep_checkpoints and n % self.C == 0:
                 p.save(self.ckpt[n // self.C])
             if self.obs_begin <= n:
-                J += p.energy()
+                p.energy_accumulate(acc)
             if n < N:
                 p.step(1)
-        return J / (self.obs_end - self.obs_begin)
+        return acc.cpu().numpy() / (self.obs_end - self.obs_begin)
 
     def forward(self, amps) -> np.ndarray:
         """Forward run keeping checkpoints for :meth:`backward`; returns J."""
@@ -96,12 +100,8 @@ class EnergyAdjoint:
         while cursor >= 0:
             k = cursor // self.C
             start = k * self.C
-            p.load(self.ckpt[k], start)
             count = cursor - start + 1
-            for j in range(count):       # recompute the segment's states
-                p.save(self.ring[j])
-                if j + 1 < count:
-                    p.step(1)
+            p.recompute(self.ckpt[k], start, self.ring, count)   # the segment's states
             p.adjoint_step(self.ring[:count], grad, count)
             cursor = start - 1
         e1.record()

@@ -15,90 +15,107 @@
 
 namespace lbm {
 
+// The adjoint is templated on R, the type of the adjoint state and of the
+// vector-Jacobian arithmetic (float or double); the forward state is decoded
+// to float as in the forward kernel, then promoted to R.
+
 // mu_j(y) = lambda_j(y + c_j) if y + c_j is fluid, else lambda_opp(j)(y):
 // the transpose of the pull gather with halfway bounce-back.
-template <int J = 0>
-__device__ __forceinline__ void gather_transpose(const float *__restrict__ lam, int pstride, int P, const int (&col)[9],
-                                                 int k, int z, int zm, int zp, float (&mu)[27])
+template <typename R, int J = 0>
+__device__ __forceinline__ void gather_transpose(const R *__restrict__ lam, int pstride, int P, const int (&col)[9],
+                                                 int k, int z, int zm, int zp, R (&mu)[27])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
     constexpr int d = NSLOT(cx, cy);
     const int zs = cz == 0 ? z : (cz > 0 ? zp : zm);
     const int sc = col[d];
     if (d == 4 || sc >= 0)
-        mu[J] = lam[J * pstride + zs * P + sc];
+        mu[J] = lam[(size_t)J * pstride + (size_t)zs * P + sc];
     else
-        mu[J] = lam[OPP(J) * pstride + z * P + k];
-    if constexpr (J + 1 < 27) gather_transpose<J + 1>(lam, pstride, P, col, k, z, zm, zp, mu);
+        mu[J] = lam[(size_t)OPP(J) * pstride + (size_t)z * P + k];
+    if constexpr (J + 1 < 27) gather_transpose<R, J + 1>(lam, pstride, P, col, k, z, zm, zp, mu);
 }
 
-__device__ __forceinline__ float hsel(int c) { return c == 0 ? -3.f : 6.f; }  // d''_c
+// per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
+// forward collision): d_0 = -3u^2/2, d_+-1 = +-3u + 3u^2; d' and d'' below
+template <typename R> struct AxisR {
+    R e0, ep, em;   // 1 + d_c
+    R q0, qp, qm;   // d'_c
+};
+template <typename R> __device__ __forceinline__ AxisR<R> axis_r(R u)
+{
+    const R u2 = u * u, u3 = R(3) * u;
+    return AxisR<R>{R(1) - R(1.5) * u2, R(1) + u3 + R(3) * u2, R(1) - u3 + R(3) * u2, -u3, R(3) + R(6) * u,
+                    R(-3) + R(6) * u};
+}
+template <int C, typename R> __device__ __forceinline__ R esel(const AxisR<R> &a) { return C == 0 ? a.e0 : (C > 0 ? a.ep : a.em); }
+template <int C, typename R> __device__ __forceinline__ R qsel_r(const AxisR<R> &a) { return C == 0 ? a.q0 : (C > 0 ? a.qp : a.qm); }
 
-struct PopAdj {
-    float Sr, Sux, Suy, Suz, Sax, Say, Saz;
+template <typename R> struct PopAdj {
+    R Sr, Sux, Suy, Suz, Sax, Say, Saz;
 };
 
 // population part: sum_i mu_i d/d(rho, u, a) [ (f^eq_i - w_i) + F_i/2 ]
-template <int I = 0>
-__device__ __forceinline__ void pop_adjoint(const CollideCtx &c, const float (&mu)[27], PopAdj &s)
+template <typename R, typename W, int I = 0>
+__device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y, const AxisR<R> &Z, R ax, R ay, R az,
+                                            const R (&mu)[27], PopAdj<R> &s)
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    const float dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y), dz = dsel<cz>(c.Z);
-    const float qx = qsel<cx>(c.X), qy = qsel<cy>(c.Y), qz = qsel<cz>(c.Z);
-    constexpr float hx = cx == 0 ? -3.f : 6.f, hy = cy == 0 ? -3.f : 6.f, hz = cz == 0 ? -3.f : 6.f;
-    const float ex = 1.f + dx, ey = 1.f + dy, ez = 1.f + dz;
-    const float eyz = ey * ez, exz = ex * ez, exy = ex * ey;
-    const float pi = ex * eyz;
-    const float px = qx * eyz, py = qy * exz, pz = qz * exy;      // d Pi / d u
-    const float api = c.ax * px + c.ay * py + c.az * pz;           // F_i / (rho w)
-    const float pxy = qx * qy * ez, pxz = qx * qz * ey, pyz = qy * qz * ex;
-    const float dax = c.ax * hx * eyz + c.ay * pxy + c.az * pxz;   // d api / d u_x
-    const float day = c.ax * pxy + c.ay * hy * exz + c.az * pyz;
-    const float daz = c.ax * pxz + c.ay * pyz + c.az * hz * exy;
-    const float wm = WGT(I) * mu[I];
-    s.Sr += wm * (pi + 0.5f * api);
-    s.Sux += wm * (px + 0.5f * dax);
-    s.Suy += wm * (py + 0.5f * day);
-    s.Suz += wm * (pz + 0.5f * daz);
+    const R ex = esel<cx>(X), ey = esel<cy>(Y), ez = esel<cz>(Z);
+    const R qx = qsel_r<cx>(X), qy = qsel_r<cy>(Y), qz = qsel_r<cz>(Z);
+    const R hx = cx == 0 ? R(-3) : R(6), hy = cy == 0 ? R(-3) : R(6), hz = cz == 0 ? R(-3) : R(6);
+    const R eyz = ey * ez, exz = ex * ez, exy = ex * ey;
+    const R pi = ex * eyz;
+    const R px = qx * eyz, py = qy * exz, pz = qz * exy;      // d Pi / d u
+    const R api = ax * px + ay * py + az * pz;                // F_i / (rho w)
+    const R pxy = qx * qy * ez, pxz = qx * qz * ey, pyz = qy * qz * ex;
+    const R dax = ax * hx * eyz + ay * pxy + az * pxz;         // d api / d u_x
+    const R day = ax * pxy + ay * hy * exz + az * pyz;
+    const R daz = ax * pxz + ay * pyz + az * hz * exy;
+    const R wm = R(wgt<W>(I)) * mu[I];  // the forward's weights (type W)
+    s.Sr += wm * (pi + R(0.5) * api);
+    s.Sux += wm * (px + R(0.5) * dax);
+    s.Suy += wm * (py + R(0.5) * day);
+    s.Suz += wm * (pz + R(0.5) * daz);
     s.Sax += wm * px;
     s.Say += wm * py;
     s.Saz += wm * pz;
-    if constexpr (I + 1 < 27) pop_adjoint<I + 1>(c, mu, s);
+    if constexpr (I + 1 < 27) pop_adjoint<R, W, I + 1>(X, Y, Z, ax, ay, az, mu, s);
 }
 
 // D_k = <mu, d_k>, the columns 4..8 of the inverse moment matrix
-template <int I = 0>
-__device__ __forceinline__ void dual_dots(const float (&mu)[27], float (&D)[5])
+template <typename R, int I = 0>
+__device__ __forceinline__ void dual_dots(const R (&mu)[27], R (&D)[5])
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    const float m = mu[I];
+    const R m = mu[I];
     if constexpr (SHELL(I) == 2) {
-        if constexpr (cz == 0) D[0] += (cx * cy > 0 ? 0.25f : -0.25f) * m;
-        if constexpr (cy == 0) D[1] += (cx * cz > 0 ? 0.25f : -0.25f) * m;
-        if constexpr (cx == 0) D[2] += (cy * cz > 0 ? 0.25f : -0.25f) * m;
+        if constexpr (cz == 0) D[0] += (cx * cy > 0 ? R(0.25) : R(-0.25)) * m;
+        if constexpr (cy == 0) D[1] += (cx * cz > 0 ? R(0.25) : R(-0.25)) * m;
+        if constexpr (cx == 0) D[2] += (cy * cz > 0 ? R(0.25) : R(-0.25)) * m;
     }
     if constexpr (SHELL(I) == 1) {
-        if constexpr (cy != 0) D[3] -= m * (1.f / 3.f);
-        else D[3] += m * (1.f / 6.f);
-        if constexpr (cz != 0) D[4] -= m * (1.f / 3.f);
-        else D[4] += m * (1.f / 6.f);
+        if constexpr (cy != 0) D[3] -= m * (R(1) / R(3));
+        else D[3] += m * (R(1) / R(6));
+        if constexpr (cz != 0) D[4] -= m * (R(1) / R(3));
+        else D[4] += m * (R(1) / R(6));
     }
-    if constexpr (I + 1 < 27) dual_dots<I + 1>(mu, D);
+    if constexpr (I + 1 < 27) dual_dots<R, I + 1>(mu, D);
 }
 
-template <int J = 0>
-__device__ __forceinline__ void write_lambda(float *__restrict__ lam, int pstride, int off, float Ldr, float Ljx,
-                                             float Ljy, float Ljz, const float (&Dp)[5])
+template <typename R, int J = 0>
+__device__ __forceinline__ void write_lambda(R *__restrict__ lam, int pstride, size_t off, R Ldr, R Ljx, R Ljy, R Ljz,
+                                             const R (&Dp)[5])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
-    float v = Ldr + cx * Ljx + cy * Ljy + cz * Ljz;
-    v += (cx * cy) * Dp[0] + (cx * cz) * Dp[1] + (cy * cz) * Dp[2];
-    v += (cx * cx - cy * cy) * Dp[3] + (cx * cx - cz * cz) * Dp[4];
-    lam[J * pstride + off] = v;
-    if constexpr (J + 1 < 27) write_lambda<J + 1>(lam, pstride, off, Ldr, Ljx, Ljy, Ljz, Dp);
+    R v = Ldr + R(cx) * Ljx + R(cy) * Ljy + R(cz) * Ljz;
+    v += R(cx * cy) * Dp[0] + R(cx * cz) * Dp[1] + R(cy * cz) * Dp[2];
+    v += R(cx * cx - cy * cy) * Dp[3] + R(cx * cx - cz * cz) * Dp[4];
+    lam[(size_t)J * pstride + off] = v;
+    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(lam, pstride, off, Ldr, Ljx, Ljy, Ljz, Dp);
 }
 
-template <typename T, int BLOCK>
+template <typename T, typename R, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
@@ -113,61 +130,81 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, 
     const float *fs = g.fshape + (size_t)b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const float sig = (a.cursor >= 0 && a.cursor < g.n_sigma) ? g.sigma[a.cursor] : 0.f;
-    const float *lin = a.lam_in + (size_t)b * g.pipe;
-    float *lout = a.lam_out + (size_t)b * g.pipe;
-    const float om1 = 1.f - g.omega;
-    const float we = (float)a.energy_weight;
+    const R *lin = (const R *)a.lam_in + (size_t)b * g.pipe;
+    R *lout = (R *)a.lam_out + (size_t)b * g.pipe;
+    const R om1 = R(1) - R(g.omega);
+    const R we = R(a.energy_weight);
     double G[3] = {0.0, 0.0, 0.0};
     const int z0 = zc * t.zchunk, z1 = min(z0 + t.zchunk, g.nz);
     for (int z = z0; z < z1; ++z) {
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        float v[27];
+        using W = typename RealOf<T>::type;
+        W v[27];
         gather<T>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
         const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
-        const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
-        const Moments m = moments_of(v);
-        float ux, uy, uz;
-        const CollideCtx c = collide_setup(m, ax, ay, az, g.omega, ux, uy, uz);
-        const float rho = c.rho;
-        float mu[27];
+        // the forward step's body acceleration (computed in its arithmetic type W), then promoted
+        W fax, fay, faz;
+        if constexpr (sizeof(W) == 4) {
+            fax = sig * cz * px;
+            fay = sig * cz * py;
+            faz = g.accel_z + sig * sz * pq;
+        } else {
+            fax = W(sig) * W(cz) * W(px);
+            fay = W(sig) * W(cz) * W(py);
+            faz = W(g.accel_z) + W(sig) * W(sz) * W(pq);
+        }
+        const R ax = R(fax), ay = R(fay), az = R(faz);
+        R dr = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const R vi = R(v[i]);
+            dr += vi;
+            jx += R(CX(i)) * vi;
+            jy += R(CY(i)) * vi;
+            jz += R(CZ(i)) * vi;
+        }
+        const R rho = R(1) + dr;
+        const R inv = R(1) / rho;
+        const R ux = jx * inv + R(0.5) * ax, uy = jy * inv + R(0.5) * ay, uz = jz * inv + R(0.5) * az;
+        const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
+        R mu[27];
         if (a.has_next) {
-            gather_transpose(lin, g.pstride, g.P, col, k, z, zm, zp, mu);
+            gather_transpose<R>(lin, g.pstride, g.P, col, k, z, zm, zp, mu);
         } else {
 #pragma unroll
-            for (int i = 0; i < 27; ++i) mu[i] = 0.f;
+            for (int i = 0; i < 27; ++i) mu[i] = R(0);
         }
-        PopAdj s = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        pop_adjoint(c, mu, s);
-        float D[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        dual_dots(mu, D);
-        float Dp[5];
+        PopAdj<R> s = {0, 0, 0, 0, 0, 0, 0};
+        pop_adjoint<R, W>(X, Y, Z, ax, ay, az, mu, s);
+        R D[5] = {0, 0, 0, 0, 0};
+        dual_dots<R>(mu, D);
+        R Dp[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) Dp[q] = om1 * D[q];
+        const R h = R(0.5);
         // moment part: sum_k D'_k (-m^eq_k + R_k / 2), printed m_4..8^eq and R_4..8
-        const float Qr = Dp[0] * (-ux * uy + 0.5f * (ay * ux + ax * uy)) + Dp[1] * (-ux * uz + 0.5f * (az * ux + ax * uz)) +
-                         Dp[2] * (-uy * uz + 0.5f * (az * uy + ay * uz)) +
-                         Dp[3] * (-(ux * ux - uy * uy) + (ax * ux - ay * uy)) +
-                         Dp[4] * (-(ux * ux - uz * uz) + (ax * ux - az * uz));
-        const float Qux = rho * (Dp[0] * (-uy + 0.5f * ay) + Dp[1] * (-uz + 0.5f * az) + (Dp[3] + Dp[4]) * (-2.f * ux + ax));
-        const float Quy = rho * (Dp[0] * (-ux + 0.5f * ax) + Dp[2] * (-uz + 0.5f * az) + Dp[3] * (2.f * uy - ay));
-        const float Quz = rho * (Dp[1] * (-ux + 0.5f * ax) + Dp[2] * (-uy + 0.5f * ay) + Dp[4] * (2.f * uz - az));
-        const float Qax = rho * (0.5f * Dp[0] * uy + 0.5f * Dp[1] * uz + (Dp[3] + Dp[4]) * ux);
-        const float Qay = rho * (0.5f * Dp[0] * ux + 0.5f * Dp[2] * uz - Dp[3] * uy);
-        const float Qaz = rho * (0.5f * Dp[1] * ux + 0.5f * Dp[2] * uy - Dp[4] * uz);
-        float Lr = s.Sr + Qr;
-        float Lux = rho * s.Sux + Qux, Luy = rho * s.Suy + Quy, Luz = rho * s.Suz + Quz;
+        const R Qr = Dp[0] * (-ux * uy + h * (ay * ux + ax * uy)) + Dp[1] * (-ux * uz + h * (az * ux + ax * uz)) +
+                     Dp[2] * (-uy * uz + h * (az * uy + ay * uz)) + Dp[3] * (-(ux * ux - uy * uy) + (ax * ux - ay * uy)) +
+                     Dp[4] * (-(ux * ux - uz * uz) + (ax * ux - az * uz));
+        const R Qux = rho * (Dp[0] * (-uy + h * ay) + Dp[1] * (-uz + h * az) + (Dp[3] + Dp[4]) * (R(-2) * ux + ax));
+        const R Quy = rho * (Dp[0] * (-ux + h * ax) + Dp[2] * (-uz + h * az) + Dp[3] * (R(2) * uy - ay));
+        const R Quz = rho * (Dp[1] * (-ux + h * ax) + Dp[2] * (-uy + h * ay) + Dp[4] * (R(2) * uz - az));
+        const R Qax = rho * (h * Dp[0] * uy + h * Dp[1] * uz + (Dp[3] + Dp[4]) * ux);
+        const R Qay = rho * (h * Dp[0] * ux + h * Dp[2] * uz - Dp[3] * uy);
+        const R Qaz = rho * (h * Dp[1] * ux + h * Dp[2] * uy - Dp[4] * uz);
+        R Lr = s.Sr + Qr;
+        R Lux = rho * s.Sux + Qux, Luy = rho * s.Suy + Quy, Luz = rho * s.Suz + Quz;
         if (a.in_window) {  // E = 1/2 rho u_z^2 with weight 1/(W N_f)
-            Lr += we * 0.5f * uz * uz;
+            Lr += we * h * uz * uz;
             Luz += we * rho * uz;
         }
         // chain rule through u = j/rho + a/2
-        const float inv = __builtin_amdgcn_rcpf(rho);
-        const float Ljx = Lux * inv, Ljy = Luy * inv, Ljz = Luz * inv;
-        const float Ldr = Lr - (Lux * (ux - 0.5f * ax) + Luy * (uy - 0.5f * ay) + Luz * (uz - 0.5f * az)) * inv;
-        const float sx = 0.5f * rho * s.Sax + Qax + 0.5f * Lux;
-        const float sy = 0.5f * rho * s.Say + Qay + 0.5f * Luy;
-        const float sz_ = 0.5f * rho * s.Saz + Qaz + 0.5f * Luz;
-        write_lambda(lout, g.pstride, z * g.P + k, Ldr, Ljx, Ljy, Ljz, Dp);
+        const R Ljx = Lux * inv, Ljy = Luy * inv, Ljz = Luz * inv;
+        const R Ldr = Lr - (Lux * (ux - h * ax) + Luy * (uy - h * ay) + Luz * (uz - h * az)) * inv;
+        const R sx = h * rho * s.Sax + Qax + h * Lux;
+        const R sy = h * rho * s.Say + Qay + h * Luy;
+        const R sz_ = h * rho * s.Saz + Qaz + h * Luz;
+        write_lambda<R>(lout, g.pstride, (size_t)z * g.P + k, Ldr, Ljx, Ljy, Ljz, Dp);
         G[0] += (double)cz * (double)sx;
         G[1] += (double)cz * (double)sy;
         G[2] += (double)sz * (double)sz_;
@@ -219,13 +256,23 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ cols
     if (threadIdx.x == 0) grad[(size_t)b * nq + q] += sigma * lds[0];
 }
 
-hipError_t launch_adjoint(int storage, const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s)
+hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
+                          hipStream_t s)
 {
     const dim3 grid((unsigned)(t.count() * t.nb));
-    if (storage == 1)
-        hipLaunchKernelGGL((k_adjoint<__half, 256>), grid, dim3(256), 0, s, g, t, a);
-    else
-        hipLaunchKernelGGL((k_adjoint<float, 256>), grid, dim3(256), 0, s, g, t, a);
+    if (storage == 2) {  // FP64 forward: FP64 adjoint
+        hipLaunchKernelGGL((k_adjoint<double, double, 256>), grid, dim3(256), 0, s, g, t, a);
+    } else if (precision == 2) {
+        if (storage == 1)
+            hipLaunchKernelGGL((k_adjoint<__half, double, 256>), grid, dim3(256), 0, s, g, t, a);
+        else
+            hipLaunchKernelGGL((k_adjoint<float, double, 256>), grid, dim3(256), 0, s, g, t, a);
+    } else {
+        if (storage == 1)
+            hipLaunchKernelGGL((k_adjoint<__half, float, 256>), grid, dim3(256), 0, s, g, t, a);
+        else
+            hipLaunchKernelGGL((k_adjoint<float, float, 256>), grid, dim3(256), 0, s, g, t, a);
+    }
     return hipGetLastError();
 }
 

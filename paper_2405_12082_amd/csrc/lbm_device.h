@@ -41,6 +41,20 @@ __host__ __device__ constexpr float WGT(int i)
 {
     return SHELL(i) == 0 ? 8.0f / 27.0f : SHELL(i) == 1 ? 2.0f / 27.0f : SHELL(i) == 2 ? 1.0f / 54.0f : 1.0f / 216.0f;
 }
+// the same weights as exact rationals in the arithmetic type R
+template <typename R> __host__ __device__ constexpr R wgt(int i)
+{
+    return SHELL(i) == 0 ? R(8) / R(27) : SHELL(i) == 1 ? R(2) / R(27) : SHELL(i) == 2 ? R(1) / R(54) : R(1) / R(216);
+}
+// arithmetic type of a storage type: FP64 storage computes in FP64, FP32 and
+// FP16 storage compute in FP32
+template <typename T> struct RealOf { using type = float; };
+template <> struct RealOf<double> { using type = double; };
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+
 // FP16 storage scale 2^k ~ 1/w_i (exact power of two: the scaling is lossless)
 __host__ __device__ constexpr float H_SCALE(int i)
 {
@@ -67,6 +81,16 @@ template <> struct Codec<float> {
     template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v)
     {
         __builtin_nontemporal_store(v, reinterpret_cast<float *>(base + off));
+    }
+};
+template <> struct Codec<double> {
+    template <int I> __device__ static __forceinline__ double ld(const char *base, unsigned off)
+    {
+        return *reinterpret_cast<const double *>(base + off);
+    }
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, double v)
+    {
+        __builtin_nontemporal_store(v, reinterpret_cast<double *>(base + off));
     }
 };
 template <> struct Codec<__half> {
@@ -116,12 +140,12 @@ __device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, cons
 // case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
 // (periodic in z).
 template <typename T, int I>
-__device__ __forceinline__ float pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
+__device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
     constexpr int d = NSLOT(-cx, -cy);
     const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
-    float v = Codec<T>::template ld<I>(p.base + I * p.pbytes, zs + p.colo[d]);
+    typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + I * p.pbytes, zs + p.colo[d]);
     if constexpr (d != 4) {
         if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(I) * p.pbytes, zo + p.own);
     }
@@ -129,14 +153,15 @@ __device__ __forceinline__ float pull_one(const Pull<T> &p, unsigned zo, unsigne
 }
 
 template <typename T, int I = 0>
-__device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo, float (&g)[27])
+__device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo,
+                                       typename RealOf<T>::type (&g)[27])
 {
     g[I] = pull_one<T, I>(p, zo, zmo, zpo);
     if constexpr (I + 1 < 27) gather<T, I + 1>(p, zo, zmo, zpo, g);
 }
 
 template <typename T, int I = 0>
-__device__ __forceinline__ void store_all(char *pipe, size_t pbytes, unsigned off, const float (&g)[27])
+__device__ __forceinline__ void store_all(char *pipe, size_t pbytes, unsigned off, const typename RealOf<T>::type (&g)[27])
 {
     Codec<T>::template st<I>(pipe + I * pbytes, off, g[I]);
     if constexpr (I + 1 < 27) store_all<T, I + 1>(pipe, pbytes, off, g);
@@ -151,22 +176,22 @@ __host__ __device__ constexpr int IDX(int cx, int cy, int cz)
 }
 
 // ---------------------------------------------------------------- moments
-struct Moments {
-    float dr;           // rho - 1 = sum g_i
-    float jx, jy, jz;   // sum c_i g_i (the weights carry no momentum)
-    float m4, m5, m6;   // sum c_x c_y g, c_x c_z g, c_y c_z g
-    float m7, m8;       // sum (c_x^2 - c_y^2) g, (c_x^2 - c_z^2) g
+template <typename R> struct Moments {
+    R dr;           // rho - 1 = sum g_i
+    R jx, jy, jz;   // sum c_i g_i (the weights carry no momentum)
+    R m4, m5, m6;   // sum c_x c_y g, c_x c_z g, c_y c_z g
+    R m7, m8;       // sum (c_x^2 - c_y^2) g, (c_x^2 - c_z^2) g
 };
 
 // Moments accumulated per in-plane group (c_x, c_y): with S = sum over c_z
 // of g, Zs = g(+1) - g(-1) and T = g(+1) + g(-1), every needed raw moment is
 // a signed sum of the group values.
-template <int G = 0>
-__device__ __forceinline__ void group_moments(const float (&g)[27], Moments &m)
+template <typename R, int G = 0>
+__device__ __forceinline__ void group_moments(const R (&g)[27], Moments<R> &m)
 {
     constexpr int cx = G % 3 - 1, cy = G / 3 - 1;
-    const float g0 = g[IDX(cx, cy, 0)], gp = g[IDX(cx, cy, 1)], gm = g[IDX(cx, cy, -1)];
-    const float T = gp + gm, S = g0 + T, Zs = gp - gm;
+    const R g0 = g[IDX(cx, cy, 0)], gp = g[IDX(cx, cy, 1)], gm = g[IDX(cx, cy, -1)];
+    const R T = gp + gm, S = g0 + T, Zs = gp - gm;
     m.dr += S;
     m.jz += Zs;
     if constexpr (cx == 1) { m.jx += S; m.m5 += Zs; }
@@ -179,13 +204,14 @@ __device__ __forceinline__ void group_moments(const float (&g)[27], Moments &m)
     if constexpr (cx == 0 && cy != 0) m.m7 -= S;
     if constexpr (cx != 0) m.m8 += S;
     m.m8 -= T;
-    if constexpr (G + 1 < 9) group_moments<G + 1>(g, m);
+    if constexpr (G + 1 < 9) group_moments<R, G + 1>(g, m);
 }
 
-__device__ __forceinline__ Moments moments_of(const float (&g)[27])
+template <typename R>
+__device__ __forceinline__ Moments<R> moments_of(const R (&g)[27])
 {
-    Moments m = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    group_moments(g, m);
+    Moments<R> m = {R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+    group_moments<R>(g, m);
     return m;
 }
 
@@ -194,57 +220,58 @@ __device__ __forceinline__ Moments moments_of(const float (&g)[27])
 // equilibrium is exactly f_i^eq = rho w_i prod_a (1 + d_{c_ia}(u_a)) with
 // d_0(u) = -3u^2/2 and d_{+-1}(u) = +-3u + 3u^2; its u-derivative uses
 // d'_0 = -3u and d'_{+-1} = +-3 + 6u.
-struct Axis {
-    float d0, dp, dm;   // d_0, d_+1, d_-1
-    float q0, qp, qm;   // derivatives
+template <typename R> struct Axis {
+    R d0, dp, dm;   // d_0, d_+1, d_-1
+    R q0, qp, qm;   // derivatives
 };
-__device__ __forceinline__ Axis axis_factors(float u)
+template <typename R> __device__ __forceinline__ Axis<R> axis_factors(R u)
 {
-    const float u2 = u * u, u3 = 3.f * u;
-    Axis a;
-    a.d0 = -1.5f * u2;
-    a.dp = u3 + 3.f * u2;
-    a.dm = -u3 + 3.f * u2;
+    const R u2 = u * u, u3 = R(3) * u;
+    Axis<R> a;
+    a.d0 = R(-1.5) * u2;
+    a.dp = u3 + R(3) * u2;
+    a.dm = -u3 + R(3) * u2;
     a.q0 = -u3;
-    a.qp = 3.f + 6.f * u;
-    a.qm = -3.f + 6.f * u;
+    a.qp = R(3) + R(6) * u;
+    a.qm = R(-3) + R(6) * u;
     return a;
 }
-template <int C> __device__ __forceinline__ float dsel(const Axis &a) { return C == 0 ? a.d0 : (C > 0 ? a.dp : a.dm); }
-template <int C> __device__ __forceinline__ float qsel(const Axis &a) { return C == 0 ? a.q0 : (C > 0 ? a.qp : a.qm); }
+template <int C, typename R> __device__ __forceinline__ R dsel(const Axis<R> &a) { return C == 0 ? a.d0 : (C > 0 ? a.dp : a.dm); }
+template <int C, typename R> __device__ __forceinline__ R qsel(const Axis<R> &a) { return C == 0 ? a.q0 : (C > 0 ? a.qp : a.qm); }
 
-struct CollideCtx {
-    Axis X, Y, Z;
-    float dr, rho;      // rho - 1 and rho
-    float ax, ay, az;   // body acceleration
-    float c4, c5, c6, c7, c8;   // (1 - omega) (m_k - m_k^eq + R_k/2), k = 4..8
+template <typename R> struct CollideCtx {
+    Axis<R> X, Y, Z;
+    R dr, rho;      // rho - 1 and rho
+    R ax, ay, az;   // body acceleration
+    R c4, c5, c6, c7, c8;   // (1 - omega) (m_k - m_k^eq + R_k/2), k = 4..8
 };
 
 // Relaxed non-equilibrium part of the stress moments, Eq. (m*) with
 // Lam_k = omega for k = 4..8: m*_k - m^eq_k - R_k/2 = (1 - omega)(m_k - m^eq_k + R_k/2),
 // using the printed m_4..8^eq and R_4..8.
-__device__ __forceinline__ CollideCtx collide_setup(const Moments &m, float ax, float ay, float az, float omega,
-                                                    float &ux, float &uy, float &uz)
+template <typename R>
+__device__ __forceinline__ CollideCtx<R> collide_setup(const Moments<R> &m, R ax, R ay, R az, R omega, R &ux, R &uy,
+                                                       R &uz)
 {
-    CollideCtx c;
+    CollideCtx<R> c;
     c.dr = m.dr;
-    c.rho = 1.f + m.dr;
-    const float inv = __builtin_amdgcn_rcpf(c.rho);
+    c.rho = R(1) + m.dr;
+    const R inv = rcp_r(c.rho);
     // Eq. (macroscopic_u): u = j/rho + a/2
-    ux = m.jx * inv + 0.5f * ax;
-    uy = m.jy * inv + 0.5f * ay;
-    uz = m.jz * inv + 0.5f * az;
+    ux = m.jx * inv + R(0.5) * ax;
+    uy = m.jy * inv + R(0.5) * ay;
+    uz = m.jz * inv + R(0.5) * az;
     c.ax = ax;
     c.ay = ay;
     c.az = az;
     c.X = axis_factors(ux);
     c.Y = axis_factors(uy);
     c.Z = axis_factors(uz);
-    const float r = c.rho, om1 = 1.f - omega;
-    const float xx = ux * ux, yy = uy * uy, zz = uz * uz;
-    c.c4 = om1 * (m.m4 - r * ux * uy + 0.5f * r * (ay * ux + ax * uy));
-    c.c5 = om1 * (m.m5 - r * ux * uz + 0.5f * r * (az * ux + ax * uz));
-    c.c6 = om1 * (m.m6 - r * uy * uz + 0.5f * r * (az * uy + ay * uz));
+    const R r = c.rho, om1 = R(1) - omega, h = R(0.5);
+    const R xx = ux * ux, yy = uy * uy, zz = uz * uz;
+    c.c4 = om1 * (m.m4 - r * ux * uy + h * r * (ay * ux + ax * uy));
+    c.c5 = om1 * (m.m5 - r * ux * uz + h * r * (az * ux + ax * uz));
+    c.c6 = om1 * (m.m6 - r * uy * uz + h * r * (az * uy + ay * uz));
     c.c7 = om1 * (m.m7 - r * (xx - yy) + r * (ax * ux - ay * uy));
     c.c8 = om1 * (m.m8 - r * (xx - zz) + r * (ax * ux - az * uz));
     return c;
@@ -258,57 +285,56 @@ __device__ __forceinline__ CollideCtx collide_setup(const Moments &m, float ax, 
 // R^MRT); d_k = columns 4..8 of the inverse moment matrix (sparse: edge links
 // for k = 4..6, face links for 7, 8).  The three populations of one in-plane
 // group (c_x, c_y) share the x-y factors.
-template <int G = 0>
-__device__ __forceinline__ void group_post_collision(const CollideCtx &c, float hr, float f7, float f8, float f9,
-                                                     float (&g)[27])
+template <typename R, int G = 0>
+__device__ __forceinline__ void group_post_collision(const CollideCtx<R> &c, R hr, R f7, R f8, R f9, R (&g)[27])
 {
     constexpr int cx = G % 3 - 1, cy = G / 3 - 1;
-    const float dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y);
-    const float qx = qsel<cx>(c.X), qy = qsel<cy>(c.Y);
-    const float exy = fmaf(dx, dy, dx + dy);   // (1+dx)(1+dy) - 1
-    const float e1 = 1.f + exy;
-    const float A = hr * fmaf(c.ax * qx, 1.f + dy, c.ay * qy * (1.f + dx));
-    const float Bz = hr * c.az * e1;
+    const R dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y);
+    const R qx = qsel<cx>(c.X), qy = qsel<cy>(c.Y);
+    const R exy = fma_r(dx, dy, dx + dy);   // (1+dx)(1+dy) - 1
+    const R e1 = R(1) + exy;
+    const R A = hr * fma_r(c.ax * qx, R(1) + dy, c.ay * qy * (R(1) + dx));
+    const R Bz = hr * c.az * e1;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const int czr = t == 0 ? 0 : (t == 1 ? 1 : -1);
-        const float dz = czr == 0 ? c.Z.d0 : (czr > 0 ? c.Z.dp : c.Z.dm);
-        const float qz = czr == 0 ? c.Z.q0 : (czr > 0 ? c.Z.qp : c.Z.qm);
-        const float pim1 = fmaf(dz, e1, exy);
-        const float feq = fmaf(pim1, c.rho, c.dr);          // (rho Pi - 1)
-        const float fh = fmaf(qz, Bz, (1.f + dz) * A);       // F / (2 w)
-        float corr = 0.f;
+        const R dz = czr == 0 ? c.Z.d0 : (czr > 0 ? c.Z.dp : c.Z.dm);
+        const R qz = czr == 0 ? c.Z.q0 : (czr > 0 ? c.Z.qp : c.Z.qm);
+        const R pim1 = fma_r(dz, e1, exy);
+        const R feq = fma_r(pim1, c.rho, c.dr);          // (rho Pi - 1)
+        const R fh = fma_r(qz, Bz, (R(1) + dz) * A);      // F / (2 w)
+        R corr = R(0);
         const int shell = cx * cx + cy * cy + czr * czr;
         if (shell == 1) corr = cx != 0 ? f7 : (cy != 0 ? f8 : f9);
         if (shell == 2) {
-            if (czr == 0) corr = (cx * cy > 0 ? 0.25f : -0.25f) * c.c4;
-            else if (cy == 0) corr = (cx * czr > 0 ? 0.25f : -0.25f) * c.c5;
-            else corr = (cy * czr > 0 ? 0.25f : -0.25f) * c.c6;
+            if (czr == 0) corr = (cx * cy > 0 ? R(0.25) : R(-0.25)) * c.c4;
+            else if (cy == 0) corr = (cx * czr > 0 ? R(0.25) : R(-0.25)) * c.c5;
+            else corr = (cy * czr > 0 ? R(0.25) : R(-0.25)) * c.c6;
         }
         const int i = t == 0 ? IDX(cx, cy, 0) : (t == 1 ? IDX(cx, cy, 1) : IDX(cx, cy, -1));
-        const float w = i == 0 ? WGT(0) : (shell == 1 ? WGT(1) : (shell == 2 ? WGT(7) : WGT(19)));
-        g[i] = fmaf(w, feq + fh, corr);
+        g[i] = fma_r(wgt<R>(i), feq + fh, corr);
     }
-    if constexpr (G + 1 < 9) group_post_collision<G + 1>(c, hr, f7, f8, f9, g);
+    if constexpr (G + 1 < 9) group_post_collision<R, G + 1>(c, hr, f7, f8, f9, g);
 }
 
-__device__ __forceinline__ void post_collision_all(const CollideCtx &c, float (&g)[27])
+template <typename R>
+__device__ __forceinline__ void post_collision_all(const CollideCtx<R> &c, R (&g)[27])
 {
     // face-link combinations of the relaxed stress moments 7 and 8
-    const float f7 = (c.c7 + c.c8) * (1.f / 6.f);             // +-x faces
-    const float f8 = c.c8 * (1.f / 6.f) - c.c7 * (1.f / 3.f);  // +-y faces
-    const float f9 = c.c7 * (1.f / 6.f) - c.c8 * (1.f / 3.f);  // +-z faces
-    group_post_collision(c, 0.5f * c.rho, f7, f8, f9, g);
+    const R f7 = (c.c7 + c.c8) * (R(1) / R(6));                   // +-x faces
+    const R f8 = c.c8 * (R(1) / R(6)) - c.c7 * (R(1) / R(3));      // +-y faces
+    const R f9 = c.c7 * (R(1) / R(6)) - c.c8 * (R(1) / R(3));      // +-z faces
+    group_post_collision<R>(c, R(0.5) * c.rho, f7, f8, f9, g);
 }
 
 // Equilibrium deviation f^eq_I(rho = 1 + dr, u) - w_I (used by the initialiser)
-template <int I>
-__device__ __forceinline__ float feq_dev(float dr, const Axis &X, const Axis &Y, const Axis &Z)
+template <int I, typename R>
+__device__ __forceinline__ R feq_dev(R dr, const Axis<R> &X, const Axis<R> &Y, const Axis<R> &Z)
 {
-    const float dx = dsel<CX(I)>(X), dy = dsel<CY(I)>(Y), dz = dsel<CZ(I)>(Z);
-    const float exy = dx + dy + dx * dy;
-    const float pim1 = exy + dz * (1.f + exy);
-    return WGT(I) * (dr * (1.f + pim1) + pim1);
+    const R dx = dsel<CX(I)>(X), dy = dsel<CY(I)>(Y), dz = dsel<CZ(I)>(Z);
+    const R exy = dx + dy + dx * dy;
+    const R pim1 = exy + dz * (R(1) + exy);
+    return wgt<R>(I) * (dr * (R(1) + pim1) + pim1);
 }
 
 // Workgroup -> tile.  remap != 0: consecutive tiles go to the same XCD

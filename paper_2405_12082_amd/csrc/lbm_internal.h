@@ -61,6 +61,8 @@ hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state,
 hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s);
 hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
 hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
+hipError_t launch_accumulate_energy(const Geom &g, const Tiles &t, const double *part, double scale, double *acc,
+                                    hipStream_t s);
 hipError_t launch_reduce_profile(const Geom &g, const Tiles &t, const double *part, double *acc, hipStream_t s);
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_set_step(long long *step_dev, long long value, int add, hipStream_t s);
@@ -69,15 +71,16 @@ hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 // adjoint
 struct AdjointArgs {
     const void *state;     // saved forward state holding S^T f^c
-    const float *lam_in;   // lambda^{c+1} (stored plainly: lambda_i at its own node)
-    float *lam_out;        // lambda^c
+    const void *lam_in;    // lambda^{c+1} (stored plainly: lambda_i at its own node), float or double
+    void *lam_out;         // lambda^c
     double *grad_part;     // [B][nzc][P][3]: FP64 per-column force sensitivities
     long long cursor;      // c
     int in_window;         // c in [obs_begin, obs_end)
     int has_next;          // c + 1 was collided (lambda^{c+1} nonzero)
     double energy_weight;  // 1 / (W N_f)
 };
-hipError_t launch_adjoint(int storage, const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s);
+hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
+                          hipStream_t s);
 hipError_t launch_project_grad(const Geom &g, const Tiles &t, const double *grad_part, double *colsum,
                                const double *mode_shape, int nq, double sigma, double *grad, hipStream_t s);
 

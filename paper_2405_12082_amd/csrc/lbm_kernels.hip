@@ -59,16 +59,35 @@ __device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : 
 #define LBM_OCCUPANCY
 #endif
 
-template <typename T>
-__device__ __forceinline__ void collide_store(const Geom &g, float (&v)[27], float sig, float px, float py, float pq,
-                                              int z, char *pout, size_t pbytes, unsigned off)
+// body acceleration a(x, n) = h z^ + sigma(n) (C_z P_x, C_z P_y, S_z Q), in the
+// arithmetic type (FP32 tables promoted for FP64 storage)
+template <typename R>
+__device__ __forceinline__ void body_force(const Geom &g, int z, float sig, float px, float py, float pq, R &ax, R &ay,
+                                           R &az)
 {
     const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
-    const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
-    const Moments m = moments_of(v);
-    float ux, uy, uz;
-    const CollideCtx c = collide_setup(m, ax, ay, az, g.omega, ux, uy, uz);
-    post_collision_all(c, v);
+    if constexpr (sizeof(R) == 4) {
+        ax = sig * cz * px;
+        ay = sig * cz * py;
+        az = g.accel_z + sig * sz * pq;
+    } else {
+        ax = R(sig) * R(cz) * R(px);
+        ay = R(sig) * R(cz) * R(py);
+        az = R(g.accel_z) + R(sig) * R(sz) * R(pq);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void collide_store(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px,
+                                              float py, float pq, int z, char *pout, size_t pbytes, unsigned off)
+{
+    using R = typename RealOf<T>::type;
+    R ax, ay, az;
+    body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
+    const Moments<R> m = moments_of<R>(v);
+    R ux, uy, uz;
+    const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, R(g.omega), ux, uy, uz);
+    post_collision_all<R>(c, v);
     store_all<T>(pout, pbytes, off, v);
 }
 
@@ -91,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, cons
     const int z0 = tc.zc * t.zchunk;
     const int z1 = min(z0 + t.zchunk, g.nz);
 #if LBM_PREFETCH
-    float cur[27], nxt[27];
+    typename RealOf<T>::type cur[27], nxt[27];
     gather<T>(p, (unsigned)z0 * rowb, (unsigned)wrap_m(z0, g.nz) * rowb, (unsigned)wrap_p(z0, g.nz) * rowb, cur);
     for (int z = z0; z < z1; ++z) {
         const int zn = z + 1 < z1 ? z + 1 : z;  // the last plane reloads itself (cached, in bounds)
@@ -103,7 +122,7 @@ __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, cons
 #else
     for (int z = z0; z < z1; ++z) {
         const unsigned zo = (unsigned)z * rowb;
-        float v[27];
+        typename RealOf<T>::type v[27];
         gather<T>(p, zo, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
         collide_store<T>(g, v, sig, px, py, pq, z, pout, p.pbytes, zo + p.own);
     }
@@ -184,15 +203,16 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
         const unsigned rowb = (unsigned)g.P * sizeof(T);
         const int z0 = tc.zc * t.zchunk;
         const int z1 = min(z0 + t.zchunk, g.nz);
+        using R = typename RealOf<T>::type;
         for (int z = z0; z < z1; ++z) {
-            float v[27];
+            R v[27];
             gather<T>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
-            const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
-            const float ax = sig * cz * px, ay = sig * cz * py, az = g.accel_z + sig * sz * pq;
-            const Moments m = moments_of(v);
-            const float rho = 1.f + m.dr;
-            const float inv = __builtin_amdgcn_rcpf(rho);
-            const float ux = m.jx * inv + 0.5f * ax, uy = m.jy * inv + 0.5f * ay, uz = m.jz * inv + 0.5f * az;
+            R ax, ay, az;
+            body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
+            const Moments<R> m = moments_of<R>(v);
+            const R rho = R(1) + m.dr;
+            const R inv = rcp_r(rho);
+            const R ux = m.jx * inv + R(0.5) * ax, uy = m.jy * inv + R(0.5) * ay, uz = m.jz * inv + R(0.5) * az;
             const size_t node = ((size_t)tc.b * g.nz + z) * plane + (size_t)y * g.nx + x;
             if (o.flags & OBS_MOMENTS) {
                 if (o.rho) o.rho[node] = rho;
@@ -283,6 +303,23 @@ __global__ __launch_bounds__(256) void k_reduce_tiles(const double *__restrict__
         for (int q = 0; q < NV; ++q) out[b * NV + q] = lds[q];
 }
 
+// acc[b] += scale * (sum of the pipe's tile partials), fixed order
+__global__ __launch_bounds__(256) void k_accumulate_tiles(const double *__restrict__ part, long long tiles_per_pipe,
+                                                          double scale, double *__restrict__ acc)
+{
+    __shared__ double lds[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (long long t = threadIdx.x; t < tiles_per_pipe; t += 256) s += part[(size_t)b * tiles_per_pipe + t];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[b] += scale * lds[0];
+}
+
 // acc[b][k][5] += sum over z-chunks of the per-chunk partials, in order
 __global__ __launch_bounds__(256) void k_reduce_profile(const double *__restrict__ part, double *__restrict__ acc,
                                                         int nzc, int P, int ncol, int B)
@@ -306,16 +343,18 @@ __global__ __launch_bounds__(256) void k_reduce_profile(const double *__restrict
 // fluid, else g_opp(j)(y) (inverse of the bounce-back pull).
 template <typename T, int J = 0>
 __device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&col)[9], const float *u0, int k,
-                                           int z, const Axis &zero, const Axis &own)
+                                           int z, const Axis<typename RealOf<T>::type> &zero,
+                                           const Axis<typename RealOf<T>::type> &own)
 {
+    using R = typename RealOf<T>::type;
     constexpr int cx = CX(J), cy = CY(J);
     const int sc = col[NSLOT(cx, cy)];
-    float v;
+    R v;
     if (sc >= 0) {
-        const Axis a = axis_factors(u0[sc]);
-        v = feq_dev<J>(0.f, zero, zero, a);
+        const Axis<R> a = axis_factors(R(u0[sc]));
+        v = feq_dev<J, R>(R(0), zero, zero, a);
     } else {
-        v = feq_dev<OPP(J)>(0.f, zero, zero, own);
+        v = feq_dev<OPP(J), R>(R(0), zero, zero, own);
     }
     Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
     if constexpr (J + 1 < 27) init_slots<T, J + 1>(pipe, g, col, u0, k, z, zero, own);
@@ -333,7 +372,8 @@ __global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restr
     const int z = (int)(r % g.nz), b = (int)(r / g.nz);
     int col[9];
     load_columns(g, k, col);
-    const Axis zero = axis_factors(0.f), own = axis_factors(u0[k]);
+    using R = typename RealOf<T>::type;
+    const Axis<R> zero = axis_factors(R(0)), own = axis_factors(R(u0[k]));
     init_slots<T>(state + (size_t)b * g.pipe, g, col, u0, k, z, zero, own);
 }
 
@@ -403,7 +443,9 @@ static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *d
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
 {
     const dim3 grid(grid_of(t));
-    if (storage == 1)
+    if (storage == 2)
+        hipLaunchKernelGGL((k_stream_copy<double, 256>), grid, dim3(256), 0, s, g, t, (const double *)src, (double *)dst);
+    else if (storage == 1)
         hipLaunchKernelGGL((k_stream_copy<unsigned short, 256>), grid, dim3(256), 0, s, g, t, (const unsigned short *)src,
                            (unsigned short *)dst);
     else
@@ -413,6 +455,7 @@ hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const 
 
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
 {
+    if (storage == 2) return step_t<double>(g, t, src, dst, off, s);
     return storage == 1 ? step_t<__half>(g, t, src, dst, off, s) : step_t<float>(g, t, src, dst, off, s);
 }
 
@@ -420,7 +463,9 @@ hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void
                           hipStream_t s)
 {
     const dim3 grid(grid_of(t));
-    if (storage == 1)
+    if (storage == 2)
+        hipLaunchKernelGGL((k_observe<double, 256>), grid, dim3(256), 0, s, g, t, (const double *)state, o, off);
+    else if (storage == 1)
         hipLaunchKernelGGL((k_observe<__half, 256>), grid, dim3(256), 0, s, g, t, (const __half *)state, o, off);
     else
         hipLaunchKernelGGL((k_observe<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)state, o, off);
@@ -435,7 +480,9 @@ static dim3 node_grid(const Geom &g)
 
 hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s)
 {
-    if (storage == 1)
+    if (storage == 2)
+        hipLaunchKernelGGL((k_init<double>), node_grid(g), dim3(256), 0, s, g, u0, (double *)state);
+    else if (storage == 1)
         hipLaunchKernelGGL((k_init<__half>), node_grid(g), dim3(256), 0, s, g, u0, (__half *)state);
     else
         hipLaunchKernelGGL((k_init<float>), node_grid(g), dim3(256), 0, s, g, u0, (float *)state);
@@ -444,7 +491,9 @@ hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state,
 
 hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s)
 {
-    if (storage == 1)
+    if (storage == 2)
+        hipLaunchKernelGGL((k_set_pops<double>), node_grid(g), dim3(256), 0, s, g, pops, (double *)state);
+    else if (storage == 1)
         hipLaunchKernelGGL((k_set_pops<__half>), node_grid(g), dim3(256), 0, s, g, pops, (__half *)state);
     else
         hipLaunchKernelGGL((k_set_pops<float>), node_grid(g), dim3(256), 0, s, g, pops, (float *)state);
@@ -460,6 +509,13 @@ hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part,
 hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL((k_reduce_tiles<1>), dim3(g.B), dim3(256), 0, s, part, t.count(), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_energy(const Geom &g, const Tiles &t, const double *part, double scale, double *acc,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_accumulate_tiles, dim3(g.B), dim3(256), 0, s, part, t.count(), scale, acc);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct Layout {
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
     // workspace offsets
-    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step;
+    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
     size_t total = 0;
@@ -75,10 +75,12 @@ int build_layout(const lbm_config *cfg, Layout &L)
         if (!(c.l_frac > 0.0) || c.l0_frac < 0.0) return bad("l_frac must be > 0 and l0_frac >= 0");
         if (c.force_off_step > kMaxSigma) return bad("force_off_step must be <= 2^24");
     }
-    if (c.storage != 0 && c.storage != 1) return bad("storage must be 0 (FP32) or 1 (FP16)");
+    if (c.storage < 0 || c.storage > 2) return bad("storage must be 0 (FP32), 1 (FP16) or 2 (FP64)");
+    if (c.storage == 2 && c.adjoint == 1) return bad("the adjoint of the FP64 forward is FP64 (adjoint = 2)");
     if (c.wall != 0) return bad("wall must be 0 (halfway bounce-back)");
     if (c.pattern != 0) return bad("pattern must be 0 (two buffers)");
     if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");
+    if (c.adjoint < 0 || c.adjoint > 2) return bad("adjoint must be 0 (none), 1 (FP32) or 2 (FP64)");
     if (c.init == 1 && (c.radius <= 0.0 || !(c.u_tau >= 0.0))) return bad("log-law init needs radius > 0, u_tau >= 0");
     if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
         return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
@@ -105,7 +107,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
                       (long long)27 * c.nz * L.P);
         return bad(buf);
     }
-    L.elem = c.storage == 1 ? 2 : 4;
+    L.elem = c.storage == 1 ? 2 : (c.storage == 2 ? 8 : 4);
     const long long pipe_elems = 27LL * c.nz * L.P;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return bad("xcd_remap must be 0 or 1");
@@ -129,6 +131,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_sigma = take((size_t)L.n_sigma * sizeof(float));
     L.off_u0 = take(P * sizeof(float));
     L.off_step = take(sizeof(long long));
+    L.off_step2 = take(sizeof(long long));
     const size_t obs_tiles = (size_t)L.obs.count() * B;
     L.off_diag_part = take(obs_tiles * 5 * sizeof(double));
     L.off_diag_out = take(B * 5 * sizeof(double));
@@ -137,7 +140,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_energy_part = take(obs_tiles * sizeof(double));
     L.off_energy_out = take(B * sizeof(double));
     if (c.adjoint) {
-        const size_t lam = align_up((size_t)pipe_elems * B * sizeof(float), 256);
+        const size_t lam = align_up((size_t)pipe_elems * B * (c.adjoint == 2 ? sizeof(double) : sizeof(float)), 256);
         L.off_lam[0] = take(lam);
         L.off_lam[1] = take(lam);
         L.off_grad_part = take(B * L.obs.nzc * P * 3 * sizeof(double));
@@ -402,6 +405,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill(ws + L.off_state[0], L.state_bytes, c->stream);  // padding reads as 0
     if (e == hipSuccess) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_prof_acc, B * P * 5 * sizeof(double), c->stream);
     if (e == hipSuccess) e = launch_init(g.storage, G, (const float *)(ws + L.off_u0), c->state(0), c->stream);
@@ -583,6 +587,40 @@ int lbm_energy(lbm_ctx *c, double *host_out)
     return LBM_OK;
 }
 
+int lbm_energy_accumulate(lbm_ctx *c, double *acc)
+{
+    CHECK_CTX(c);
+    if (!acc) return fail(c, LBM_EINVAL, "lbm_energy_accumulate: NULL accumulator");
+    ObserveArgs o{};
+    o.flags = OBS_ENERGY;
+    o.energy_part = (double *)(c->ws + c->L.off_energy_part);
+    int rc = observe(c, o);
+    if (rc != LBM_OK) return rc;
+    const double nf = (double)c->L.ncol * c->cfg.nz;
+    HIPCHK(c, launch_accumulate_energy(c->geom, c->L.obs, o.energy_part, 1.0 / nf, acc, c->stream));
+    return LBM_OK;
+}
+
+int lbm_recompute(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *ring, size_t stride)
+{
+    CHECK_CTX(c);
+    if (!start || !ring || n < 1 || s0 < 0) return fail(c, LBM_EINVAL, "lbm_recompute: bad arguments");
+    if (stride < c->L.state_bytes || (stride & 255) || ((uintptr_t)ring & 255))
+        return fail(c, LBM_EINVAL, "lbm_recompute: stride must be >= the state size and ring/stride 256-byte aligned");
+    char *r = (char *)ring;
+    if (start != ring) HIPCHK(c, hipMemcpyAsync(r, start, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (n == 1) return LBM_OK;
+    Geom g = c->geom;
+    g.step_dev = (const long long *)(c->ws + c->L.off_step2);
+    HIPCHK(c, launch_set_step((long long *)(c->ws + c->L.off_step2), s0, 0, c->stream));
+    Tiles t = c->L.step;
+    t.b0 = 0;
+    t.nb = c->cfg.batch;
+    for (int j = 0; j + 1 < n; ++j)
+        HIPCHK(c, launch_step(c->cfg.storage, g, t, r + (size_t)j * stride, r + (size_t)(j + 1) * stride, j, c->stream));
+    return LBM_OK;
+}
+
 int lbm_profile_accumulate(lbm_ctx *c)
 {
     CHECK_CTX(c);
@@ -657,7 +695,7 @@ int lbm_adjoint_reset(lbm_ctx *c, int64_t obs_begin, int64_t obs_end)
     c->cursor = obs_end - 1;
     c->lam_cur = 0;
     c->adj_ready = true;
-    const size_t lam = (size_t)c->geom.pipe * c->cfg.batch * sizeof(float);
+    const size_t lam = (size_t)c->geom.pipe * c->cfg.batch * (c->cfg.adjoint == 2 ? sizeof(double) : sizeof(float));
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[0], lam, c->stream));
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[1], lam, c->stream));
     return LBM_OK;
@@ -675,14 +713,14 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
     for (int j = n - 1; j >= 0; --j) {
         AdjointArgs a{};
         a.state = (const char *)fwd_states + (size_t)j * state_stride;
-        a.lam_in = (const float *)(c->ws + c->L.off_lam[c->lam_cur]);
-        a.lam_out = (float *)(c->ws + c->L.off_lam[c->lam_cur ^ 1]);
+        a.lam_in = c->ws + c->L.off_lam[c->lam_cur];
+        a.lam_out = c->ws + c->L.off_lam[c->lam_cur ^ 1];
         a.grad_part = (double *)(c->ws + c->L.off_grad_part);
         a.cursor = c->cursor;
         a.in_window = c->cursor >= c->obs_begin && c->cursor < c->obs_end;
         a.has_next = c->cursor + 1 < c->obs_end;
         a.energy_weight = wgt;
-        HIPCHK(c, launch_adjoint(c->cfg.storage, c->geom, c->L.obs, a, c->stream));
+        HIPCHK(c, launch_adjoint(c->cfg.storage, c->cfg.adjoint, c->geom, c->L.obs, a, c->stream));
         if (nq > 0) {
             const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
             // the kernels use the FP32 table value of sigma; use the same rounding here

@@ -136,6 +136,18 @@ class Pipe:
         self._check(self.lib.lbm_energy(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))), "lbm_energy")
         return out
 
+    def energy_accumulate(self, acc: torch.Tensor):
+        """acc[b] += E_b of the current state (device FP64 tensor [batch]), no sync."""
+        self._check(self.lib.lbm_energy_accumulate(self._ctx, C.c_void_p(_ptr(acc))), "lbm_energy_accumulate")
+
+    def recompute(self, start: torch.Tensor, s0: int, ring: torch.Tensor, n: int | None = None):
+        """ring[0] := start (state of step s0), ring[j+1] := step(ring[j]); the
+        context's own state is untouched."""
+        n = ring.shape[0] if n is None else n
+        stride = ring.stride(0) * ring.element_size()
+        self._check(self.lib.lbm_recompute(self._ctx, C.c_void_p(_ptr(start)), int(s0), int(n),
+                                           C.c_void_p(_ptr(ring)), C.c_size_t(stride)), "lbm_recompute")
+
     def profile_accumulate(self):
         self._check(self.lib.lbm_profile_accumulate(self._ctx), "lbm_profile_accumulate")
 

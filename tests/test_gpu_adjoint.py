@@ -37,15 +37,33 @@ TINY = dict(nx=12, ny=12, nz=8, batch=1, radius=5.0, tau=0.6, accel_z=1e-5, n_mo
 TINY_AMPS = np.array([1e-4, 2e-4, 3e-4, 1.5e-4])
 
 
-def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod):
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod, precision):
     O = oracle_mod
-    run = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=7)
+    run = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=7, precision=precision)
     J, g = run.gradient(TINY_AMPS[None])
     Jo, go = O.adjoint_gradient(O.make_config(**TINY), TINY_AMPS, 20, 40)
     err = np.abs(g[0] - go).max() / np.abs(go).max()
     _log(f"J gpu {J[0]:.10e} oracle {Jo:.10e}; gradient error vs oracle adjoint {err:.3e}")
     assert abs(J[0] - Jo) < 1e-5 * abs(Jo)  # FP32 state: u_z to ~1e-6 relative
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-5), ("fp32", 1e-4)])
+def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol):
+    """2000 steps of a 16x16x32 pipe (R = 7) with the adjoint workload's
+    physics: the GPU adjoint (FP32 forward) against the oracle's complex-step
+    tangent of the whole FP64 run (the exact derivative)."""
+    O = oracle_mod
+    cfg = LI.preset("adjoint")
+    cfg.update(nx=16, ny=16, nz=32, radius=7.0, accel_z=2 * cfg["u_tau"] ** 2 / 7.0,
+               period=float(round(0.052 * 7.0 / cfg["u_tau"])), force_off_step=2000)
+    amps = LI.preset_amplitudes(cfg)
+    J, g = gpu.EnergyAdjoint(cfg, 1501, 2001, checkpoint_every=100, precision=precision).gradient(amps)
+    Jt, gt = O.tangent_gradient(O.make_config(**cfg), amps[0], 1501, 2001)
+    err = np.linalg.norm(g[0] - gt) / np.linalg.norm(gt)
+    _log(f"{precision} adjoint vs oracle tangent over 2000 steps: {err:.3e}")
+    assert err < tol
 
 
 def test_checkpoint_interval_does_not_change_the_gradient(gpu):

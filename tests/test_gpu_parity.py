@@ -187,6 +187,30 @@ def test_periodic_box_shear_wave(gpu, O):
     assert _vel_err(u_g[0], u_o, mask) < 1e-5
 
 
+# ------------------------------------------------------------------ FP64 reference storage
+def test_fp64_storage_forced_run(gpu, O):
+    """FP64 deviations and collision: the forced log-law run matches the
+    oracle to FP32 export precision after 50 steps (the forcing tables are FP32)."""
+    cfg = _forced_cfg(nx=30, ny=28, nz=24, radius=13.4, storage=2)
+    amps = _amps(cfg, seed=9)
+    p = gpu.Pipe(cfg, amps)
+    o = _oracle_pipe(O, cfg, amps[0])
+    p.step(50)
+    o.step(50)
+    g = p.populations().cpu().numpy()[0].astype(np.float64)  # exported as FP32
+    _, w, _ = O.lattice()
+    go = o.get_f() - w[:, None, None, None]
+    mask = o.fluid_mask()
+    err = np.abs(g[:, mask] - go[:, mask]).max() / np.abs(go[:, mask]).max()
+    _log(f"fp64 storage: population error {err:.3e} (FP32 export)")
+    assert err < 2e-7  # the export rounds to FP32
+    d = p.diagnostics(raise_on_nan=True)[0]
+    s = o.sums()
+    assert abs(d[0] - s[0]) < 1e-10 * s[0]
+    # FP32 forcing tables (sigma, cos/sin, mode shapes): ~1e-9 on the summed momentum
+    np.testing.assert_allclose(d[1:4], s[1:4], rtol=1e-8, atol=1e-12 * s[0])
+
+
 # ------------------------------------------------------------------ FP16 storage
 def test_fp16_storage_forced_run(gpu, O):
     """FP16 scaled-deviation storage, FP32 collision: velocity error against
@@ -329,3 +353,41 @@ def test_energy_matches_oracle(gpu, O):
     o.step(11)
     e = p.energy()[0]
     assert abs(e - o.energy()) < 1e-5 * o.energy()
+
+
+def test_recompute_records_the_stepped_states(gpu):
+    cfg = _forced_cfg()
+    amps = _amps(cfg)
+    p = gpu.Pipe(cfg, amps)
+    p.step(6)
+    start, s0 = p.save()
+    start = start.clone()
+    ref = []
+    for j in range(5):
+        ref.append(p.save()[0].clone())
+        p.step(1)
+    ring = torch.empty((5, p.state_bytes), dtype=torch.uint8, device="cuda")
+    p.recompute(start, s0, ring)
+    torch.cuda.synchronize()
+    ncol, P = int(p.layout.n_fluid_columns), int(p.layout.plane_pitch)
+    n = 27 * cfg["nz"] * P
+
+    def valid(blob):  # the stored columns of every (population, plane); padding excluded
+        return blob[:4 * n].view(torch.float32).reshape(27 * cfg["nz"], P)[:, :ncol]
+
+    for j in range(5):
+        assert torch.equal(valid(ring[j]), valid(ref[j])), j
+    assert p.step_index == 11  # own state untouched
+
+
+def test_energy_accumulate_matches_energy(gpu):
+    cfg = _forced_cfg(batch=2)
+    amps = _amps(cfg)
+    p = gpu.Pipe(cfg, amps)
+    acc = torch.zeros(2, dtype=torch.float64, device="cuda")
+    tot = np.zeros(2)
+    for _ in range(3):
+        p.step(4)
+        p.energy_accumulate(acc)
+        tot += p.energy()
+    np.testing.assert_allclose(acc.cpu().numpy(), tot, rtol=1e-14, atol=0)

@@ -56,3 +56,18 @@ def test_presets_follow_the_paper_relations():
     t = LI.preset("turbulent")
     assert (t["nx"], t["ny"], t["nz"], t["radius"]) == (192, 192, 1152, 90.0)
     assert LI.preset("batched")["batch"] == 64
+
+
+def test_deviation_generators_agree():
+    """The full-field (numpy and torch) and pointwise generators give the same
+    float32 values, so both sides of a parity test see identical inputs."""
+    import torch
+    shape = (5, 4, 3)
+    a = LI.random_deviations(17, shape)
+    b = LI.random_deviations_torch(17, shape, device="cpu").numpy()
+    assert np.array_equal(a, b)
+    rng = np.random.default_rng(0)
+    i = rng.integers(0, 27, 50)
+    flat = rng.integers(0, 60, 50)
+    c = LI.random_deviations_at(17, shape, i, flat)
+    assert np.array_equal(c, a.reshape(27, -1)[i, flat])
