@@ -175,7 +175,7 @@ def leg_adjoint():
         nf = p.n_fluid
         del p
         run = EnergyAdjoint(cfg, cfg["obs_begin"], cfg["obs_end"], checkpoint_every=cfg["checkpoint_every"],
-                            stream=stream)
+                            stream=stream, precision="fp32")
         J, g = run.gradient(amps)
         t = dict(run.timing)
         del run
@@ -183,7 +183,8 @@ def leg_adjoint():
     return {"steps": N, "forward_plain_ms": round(ms_fwd, 2),
             "forward_with_checkpoints_ms": round(t["forward_ms"], 2), "backward_ms": round(t["backward_ms"], 2),
             "adjoint_fwd_cost_ratio": round(t["backward_ms"] / ms_fwd, 3),
-            "J": float(J[0]), "grad_norm": float(np.linalg.norm(g[0])),
+            "J": float(J[0]), "grad_norm": float(np.linalg.norm(g[0])), "adjoint_state": "fp32",
+            "gradient_accumulation": "fp64",
             "fluid_nodes": nf, "checkpoint_every": cfg["checkpoint_every"]}
 
 

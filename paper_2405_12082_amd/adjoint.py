@@ -25,12 +25,13 @@ class EnergyAdjoint:
 
     cfg:   configuration dict (``lbm_config`` fields).
     obs_begin, obs_end: the window [obs_begin, obs_end) of J.
-    precision: "fp64" (adjoint state and vector-Jacobian arithmetic in FP64)
-    or "fp32"; the forward model is the same FP32-arithmetic stepper.
+    precision: "fp32" (default: adjoint state and vector-Jacobian arithmetic
+    in FP32, gradient accumulation in FP64) or "fp64"; the forward model is
+    the configured stepper (FP64 forward storage requires "fp64").
     """
 
     def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
-                 device="cuda", stream=None, precision: str = "fp64"):
+                 device="cuda", stream=None, precision: str = "fp32"):
         if not (0 <= obs_begin < obs_end):
             raise ValueError("need 0 <= obs_begin < obs_end")
         if precision not in ("fp32", "fp64"):
