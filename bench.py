@@ -188,6 +188,79 @@ def leg_adjoint():
             "fluid_nodes": nf, "checkpoint_every": cfg["checkpoint_every"]}
 
 
+def run_precision(steps=5000, sample_every=100, oracle_steps=100):
+    """FP32 and FP16 storage against the FP64 reference on the 64x64x256
+    precision pipe (R = 30, the turbulent workload's tau and u*): velocity
+    error at steps 100 and 1000, and the radial profiles of mean, rms,
+    skewness and flatness of u_z over the second half of the run (sampled
+    every 100 steps).  The FP64 GPU run is tied to the FP64 oracle at step
+    ``oracle_steps``."""
+    import numpy as np
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    from paper_2405_12082_amd.pipe import radial_profiles
+    from oracle import oracle as O
+    cfg = LI.preset("precision_ref")
+    amps = LI.preset_amplitudes(cfg)
+    first = cfg["force_off_step"]
+    res = {}
+    for storage in (2, 0, 1):
+        c = dict(cfg, storage=storage)
+        p = P.Pipe(c, amps)
+        snaps = {}
+        n = 0
+        for target in (oracle_steps, 1000):
+            p.step(target - n)
+            n = target
+            snaps[target] = p.moments()[1][0].cpu().numpy().astype(np.float64)
+        p.profile_reset()
+        while n < steps:
+            k = min(sample_every - n % sample_every, steps - n)
+            p.step(k)
+            n += k
+            if n >= first and n % sample_every == 0:
+                p.profile_accumulate()
+        prof = radial_profiles(p.profile_read()[0], c)
+        ok = bool(p.diagnostics()[0, 4] == 0)
+        res[storage] = (snaps, prof, ok)
+        del p
+        torch.cuda.empty_cache()
+    o = O.Pipe(O.make_config(**cfg), amps[0])
+    o.step(oracle_steps)
+    uo = o.moments()[1]
+    mask = o.fluid_mask()
+    del o
+    ref_snaps, ref_prof, _ = res[2]
+
+    def verr(u, ur):
+        return float(np.abs(u - ur)[:, mask].max() / np.abs(ur[:, mask]).max())
+
+    rmax = cfg["radius"] - 1.0
+    sel = (ref_prof["count"] > 0) & (ref_prof["r"] < rmax)
+
+    def perr(pa, key, relative=True):
+        d = np.abs(pa[key][sel] - ref_prof[key][sel]).max()
+        return float(d / np.abs(ref_prof[key][sel]).max()) if relative else float(d)
+
+    out = {"pipe": "64x64x256 R=30", "steps": steps, "stats_window": [first, steps],
+           "fp64_gpu_vs_oracle_velocity": {f"step_{oracle_steps}": verr(ref_snaps[oracle_steps], uo)}}
+    for storage, name in ((0, "fp32"), (1, "fp16")):
+        snaps, prof, ok = res[storage]
+        out[name] = {"velocity_step_100": verr(snaps[100], ref_snaps[100]),
+                     "velocity_step_1000": verr(snaps[1000], ref_snaps[1000]),
+                     "mean_profile": perr(prof, "mean"), "rms_profile": perr(prof, "rms"),
+                     "skewness_profile_abs": perr(prof, "skewness", False),
+                     "flatness_profile_abs": perr(prof, "flatness", False), "state_finite": ok}
+    out["reference_profiles"] = {k: [round(float(v), 8) for v in ref_prof[k][sel]]
+                                 for k in ("r", "mean", "rms", "skewness", "flatness")}
+    return out
+
+
+def leg_precision():
+    return run_precision()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,7 +272,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,batched,adjoint",
+    ap.add_argument("--legs", default="fp16,batched,adjoint,precision",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -327,7 +400,8 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     for leg in legs:
-        extra[leg] = {"fp16": leg_fp16, "batched": leg_batched, "adjoint": leg_adjoint}[leg]()
+        extra[leg] = {"fp16": leg_fp16, "batched": leg_batched, "adjoint": leg_adjoint,
+                      "precision": leg_precision}[leg]()
     if extra:
         out["extra"] = extra
     if not args.no_cpu_baseline:

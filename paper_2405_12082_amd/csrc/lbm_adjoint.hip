@@ -115,8 +115,17 @@ __device__ __forceinline__ void write_lambda(R *__restrict__ lam, int pstride, s
     if constexpr (J + 1 < 27) write_lambda<R, J + 1>(lam, pstride, off, Ldr, Ljx, Ljy, Ljz, Dp);
 }
 
+#ifndef LBM_ADJ_WAVES_PER_EU
+#define LBM_ADJ_WAVES_PER_EU 0
+#endif
+#if LBM_ADJ_WAVES_PER_EU > 0
+#define LBM_ADJ_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LBM_ADJ_WAVES_PER_EU)))
+#else
+#define LBM_ADJ_OCCUPANCY
+#endif
+
 template <typename T, typename R, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
+__global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc + t.b0;
