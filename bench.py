@@ -124,6 +124,14 @@ def leg_batched(steps=200, graph_k=50):
         b.record(stream)
         b.synchronize()
         ms_batched = a.elapsed_time(b) / steps
+        # the same steps as one persistent cooperative launch (grid barrier per step)
+        p.step_persistent(2)
+        a, b = _events(stream)
+        a.record(stream)
+        p.step_persistent(steps)
+        b.record(stream)
+        b.synchronize()
+        ms_persistent = a.elapsed_time(b) / steps
         nf = p.n_fluid
         ok = bool((p.diagnostics()[:, 4] == 0).all())
         del p
@@ -147,7 +155,10 @@ def leg_batched(steps=200, graph_k=50):
             "launch": tune["best"], "graph_steps": graph_k, "autotune_cached": tune["cached"],
             "sequential_single_pipes": {"value": round(B * nf / (ms_seq * 1e-3) / 1e6, 1),
                                         "ms_per_step": round(ms_seq, 4)},
-            "speedup_vs_sequential": round(ms_seq / ms_batched, 3), "state_finite": ok}
+            "speedup_vs_sequential": round(ms_seq / ms_batched, 3),
+            "persistent_launch": {"value": round(B * nf / (ms_persistent * 1e-3) / 1e6, 1),
+                                  "ms_per_step": round(ms_persistent, 4)},
+            "state_finite": ok}
 
 
 def leg_adjoint():

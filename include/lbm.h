@@ -129,6 +129,15 @@ int lbm_step(lbm_ctx *ctx, int32_t n);
  * launches for the remainder.  Async.  Same results as lbm_step. */
 int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
 
+/* Run n steps as ONE persistent cooperative launch: the co-resident
+ * workgroups are split into groups that each own whole pipes; a group's
+ * workgroups stride over its pipes' tiles and meet at a group barrier before
+ * the next step (pipes are independent, so groups never wait for each
+ * other).  Same results as lbm_step (bitwise).  The barrier's wait is
+ * bounded; if it ever times out the call returns LBM_ESTATE and the state is
+ * invalid.  Synchronises the stream. */
+int lbm_step_persistent(lbm_ctx *ctx, int32_t n);
+
 /* Change the launch geometry of lbm_step and lbm_step_graph on a live
  * context: threads per block (64, 128, 256), z planes per thread (1..64),
  * tile order (xcd_remap 0 or 1), pipes per launch (1..batch) and step order

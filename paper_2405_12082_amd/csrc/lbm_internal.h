@@ -30,7 +30,7 @@ struct Tiles {
     int xcd;  // nonzero: XCD-aware workgroup -> tile mapping
     int b0;   // first pipe of the launch
     int nb;   // pipes covered by the launch
-    long long count() const { return (long long)nkb * nzc; }
+    __host__ __device__ long long count() const { return (long long)nkb * nzc; }
 };
 
 enum ObserveFlags {
@@ -54,6 +54,11 @@ struct ObserveArgs {
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
+// persistent launch: blocks = groups * per_group workgroups, group q owning
+// pipes [q * pipes_per_group, ...); bar: 32 words per group + 32 (error flag)
+hipError_t launch_step_persistent(int storage, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
+                                  unsigned *bar, int blocks, int per_group, int pipes_per_group, hipStream_t s);
+int persistent_blocks_per_cu(int storage, int block);
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
 hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
                           int step_off, hipStream_t s);

@@ -17,9 +17,8 @@ namespace lbm {
 struct TileCoord {
     int b, zc, k, kb;
 };
-__device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
+__device__ __forceinline__ TileCoord tile_coord(const Tiles &t, int tile, int block)
 {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     TileCoord c;
     c.kb = tile % t.nkb;
     const int rest = tile / t.nkb;
@@ -27,6 +26,10 @@ __device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
     c.b = rest / t.nzc + t.b0;
     c.k = c.kb * block + threadIdx.x;
     return c;
+}
+__device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
+{
+    return tile_coord(t, xcd_tile(blockIdx.x, gridDim.x, t.xcd), block);
 }
 
 __device__ __forceinline__ void load_columns(const Geom &g, int k, int (&col)[9])
@@ -44,12 +47,8 @@ __device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : 
 __device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
 // ---------------------------------------------------------------- step
-// Tuning knobs (compile time): LBM_PREFETCH issues the 27 loads of plane
-// z+1 before the collision of plane z; LBM_WAVES_PER_EU asks the compiler
-// for a register budget allowing that many waves per SIMD.
-#ifndef LBM_PREFETCH
-#define LBM_PREFETCH 0
-#endif
+// LBM_WAVES_PER_EU (compile time) asks the compiler for a register budget
+// allowing that many waves per SIMD.
 #ifndef LBM_WAVES_PER_EU
 #define LBM_WAVES_PER_EU 0
 #endif
@@ -91,42 +90,127 @@ __device__ __forceinline__ void collide_store(const Geom &g, typename RealOf<T>:
     store_all<T>(pout, pbytes, off, v);
 }
 
-// One time step of every fluid node: pull gather (streaming + bounce-back)
-// of g(n) from S^T g(n), collision at a(x, n), aligned store of g*(n).
-template <typename T, int BLOCK>
-__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
-                                                               T *__restrict__ dst, int step_off)
+// One tile of one time step (column k of the tile, its z planes): pull
+// gather (streaming + bounce-back) of g(n) from S^T g(n), collision at
+// a(x, n), aligned store of g*(n).
+template <typename T>
+__device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *__restrict__ src,
+                                          T *__restrict__ dst, long long n)
 {
-    const TileCoord tc = decode_tile(t, BLOCK);
     const int k = tc.k;
-    if (k >= g.ncol) return;
     const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
     const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
-    const long long n = *g.step_dev + step_off;
     const float sig = sigma_of(g, n);
     char *pout = reinterpret_cast<char *>(dst + (size_t)tc.b * g.pipe);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const int z0 = tc.zc * t.zchunk;
     const int z1 = min(z0 + t.zchunk, g.nz);
-#if LBM_PREFETCH
-    typename RealOf<T>::type cur[27], nxt[27];
-    gather<T>(p, (unsigned)z0 * rowb, (unsigned)wrap_m(z0, g.nz) * rowb, (unsigned)wrap_p(z0, g.nz) * rowb, cur);
-    for (int z = z0; z < z1; ++z) {
-        const int zn = z + 1 < z1 ? z + 1 : z;  // the last plane reloads itself (cached, in bounds)
-        gather<T>(p, (unsigned)zn * rowb, (unsigned)wrap_m(zn, g.nz) * rowb, (unsigned)wrap_p(zn, g.nz) * rowb, nxt);
-        collide_store<T>(g, cur, sig, px, py, pq, z, pout, p.pbytes, (unsigned)z * rowb + p.own);
-#pragma unroll
-        for (int i = 0; i < 27; ++i) cur[i] = nxt[i];
-    }
-#else
     for (int z = z0; z < z1; ++z) {
         const unsigned zo = (unsigned)z * rowb;
         typename RealOf<T>::type v[27];
         gather<T>(p, zo, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
         collide_store<T>(g, v, sig, px, py, pq, z, pout, p.pbytes, zo + p.own);
     }
-#endif
+}
+
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
+                                                               T *__restrict__ dst, int step_off)
+{
+    const TileCoord tc = decode_tile(t, BLOCK);
+    if (tc.k >= g.ncol) return;
+    step_tile<T>(g, t, tc, src, dst, *g.step_dev + step_off);
+}
+
+// Barrier of one group of workgroups inside a cooperative launch (all
+// workgroups are co-resident).  Each group owns whole pipes, and a pipe's
+// step n+1 reads only that pipe's step n, so the groups never wait for each
+// other.  gb[0]: arrivals, gb[1]: generation, gb[2..3]: the tile counters
+// of even and odd steps (one 128-byte line per group, so the atomics of
+// different groups go to different lines); err[0]: error flag shared by all
+// groups.  After the workgroup barrier one thread fences at agent scope
+// (the release writes this XCD's L2 back, covering the stores of every wave
+// of the workgroup) and arrives; the last arrival clears the tile counter
+// of the step just finished (next used two steps later) before it bumps the
+// generation.  The wait is bounded: on timeout the error flag is set and
+// every workgroup that sees it leaves the step loop, so the grid always
+// drains.
+__device__ __forceinline__ bool group_barrier(unsigned *gb, unsigned *err, unsigned members, unsigned *done_counter)
+{
+    __syncthreads();
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        ok = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+        if (ok) {
+            const unsigned gen = __hip_atomic_load(&gb[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned arrived = __hip_atomic_fetch_add(&gb[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == members - 1) {
+                __hip_atomic_store(&gb[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(done_counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&gb[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                unsigned spins = 0;
+                while (__hip_atomic_load(&gb[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (++spins > (1u << 21)) {
+                        __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        ok = 0;
+                        break;
+                    }
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// n time steps in one launch.  Workgroup w belongs to group w / per_group;
+// group q owns pipes [q * pipes_per_group, ...).  Within a step the group's
+// workgroups take tickets of PERSIST_CHUNK consecutive tiles from the
+// group's counter (dynamic balance: a slower CU takes fewer tiles; the next
+// ticket is requested before the current tiles run, hiding the atomic's
+// latency), then meet at the group barrier before the next step.  Buffers
+// alternate: step j reads buf[(par + j) & 1].
+constexpr int PERSIST_CHUNK = 2;
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const Tiles t, T *buf0, T *buf1, int par,
+                                                           int nsteps, unsigned *bar, int per_group,
+                                                           int pipes_per_group)
+{
+    const int q = blockIdx.x / per_group;
+    const int per_pipe = (int)t.count();
+    const int b_lo = q * pipes_per_group;
+    const int b_hi = min(t.nb, b_lo + pipes_per_group);
+    const int first = b_lo * per_pipe, ntiles = (b_hi - b_lo) * per_pipe;
+    unsigned *gb = bar + 32 * (1 + q);
+    const long long n0 = *g.step_dev;
+    __shared__ int ticket;
+    for (int j = 0; j < nsteps; ++j) {
+        const T *src = ((par + j) & 1) ? buf1 : buf0;
+        T *dst = ((par + j) & 1) ? buf0 : buf1;
+        unsigned *ctr = &gb[2 + (j & 1)];
+        if (threadIdx.x == 0) ticket = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int cur = ticket;
+        while (cur * PERSIST_CHUNK < ntiles) {
+            __syncthreads();  // every thread has read the ticket before it is replaced
+            int nxt = 0;
+            if (threadIdx.x == 0) nxt = (int)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int lo = cur * PERSIST_CHUNK, hi = min(lo + PERSIST_CHUNK, ntiles);
+            for (int tile = lo; tile < hi; ++tile) {
+                const TileCoord tc = tile_coord(t, first + tile, BLOCK);
+                if (tc.k < g.ncol) step_tile<T>(g, t, tc, src, dst, n0 + j);
+            }
+            if (threadIdx.x == 0) ticket = nxt;
+            __syncthreads();
+            cur = ticket;
+        }
+        if (j + 1 < nsteps && !group_barrier(gb, bar, (unsigned)per_group, ctr)) break;
+    }
 }
 
 // Practical bandwidth ceiling of the step's access pattern: the same tiles,
@@ -451,6 +535,56 @@ hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const 
     else
         hipLaunchKernelGGL((k_stream_copy<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)src, (float *)dst);
     return hipGetLastError();
+}
+
+template <typename T, int BLOCK>
+static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
+                               int blocks, int per_group, int ppg, hipStream_t s)
+{
+    Geom gg = g;
+    Tiles tt = t;
+    T *p0 = (T *)b0, *p1 = (T *)b1;
+    void *args[] = {&gg, &tt, &p0, &p1, &par, &nsteps, &bar, &per_group, &ppg};
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK>;
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
+}
+
+template <typename T>
+static hipError_t persistent_block(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
+                                   int blocks, int per_group, int ppg, hipStream_t s)
+{
+    switch (t.block) {
+    case 64: return persistent_t<T, 64>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 128: return persistent_t<T, 128>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    default: return persistent_t<T, 256>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    }
+}
+
+hipError_t launch_step_persistent(int storage, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
+                                  unsigned *bar, int blocks, int per_group, int pipes_per_group, hipStream_t s)
+{
+    if (storage == 2)
+        return persistent_block<double>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+    if (storage == 1)
+        return persistent_block<__half>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+    return persistent_block<float>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+}
+
+template <typename T, int BLOCK> static int occ_t()
+{
+    int n = 0;
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(fn), BLOCK, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+template <typename T> static int occ_block(int block)
+{
+    return block == 64 ? occ_t<T, 64>() : (block == 128 ? occ_t<T, 128>() : occ_t<T, 256>());
+}
+int persistent_blocks_per_cu(int storage, int block)
+{
+    return storage == 2 ? occ_block<double>(block) : (storage == 1 ? occ_block<__half>(block) : occ_block<float>(block));
 }
 
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -39,7 +40,7 @@ struct Layout {
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
     // workspace offsets
-    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2;
+    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
     size_t total = 0;
@@ -134,6 +135,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_u0 = take(P * sizeof(float));
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
+    L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
     const size_t obs_tiles = (size_t)L.obs.count() * B;
     L.off_diag_part = take(obs_tiles * 5 * sizeof(double));
     L.off_diag_out = take(B * 5 * sizeof(double));
@@ -463,6 +465,41 @@ int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
         n -= reps * k;
     }
     return do_step_eager(c, n);
+}
+
+int lbm_step_persistent(lbm_ctx *c, int32_t n)
+{
+    CHECK_CTX(c);
+    if (n < 0) return fail(c, LBM_EINVAL, "lbm_step_persistent: n must be >= 0");
+    if (n == 0) return LBM_OK;
+    int dev = 0, cus = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, c->L.step.block);
+    if (per_cu < 1 || cus < 1) return fail(c, LBM_EHIP, "lbm_step_persistent: occupancy query failed");
+    Tiles t = c->L.step;
+    t.b0 = 0;
+    t.nb = c->cfg.batch;
+    // groups of workgroups own whole pipes: as many groups as pipes while the
+    // co-resident workgroups suffice, else several pipes per group
+    const long long slots = (long long)per_cu * cus, per_pipe = t.count();
+    const int B = c->cfg.batch;
+    if (per_pipe * B > INT_MAX) return fail(c, LBM_EINVAL, "lbm_step_persistent: too many tiles for one launch");
+    const int ppg = (int)((B + slots - 1) / slots);
+    const int groups = (B + ppg - 1) / ppg;
+    const int per_group = (int)std::min<long long>(slots / groups, per_pipe * ppg);
+    const int blocks = groups * per_group;
+    unsigned *bar = (unsigned *)(c->ws + c->L.off_bar);
+    HIPCHK(c, launch_fill(bar, 32 * sizeof(unsigned) * ((size_t)groups + 1), c->stream));
+    HIPCHK(c, launch_step_persistent(c->cfg.storage, c->geom, t, c->state(c->step), c->state(c->step + 1), 0, n, bar,
+                                     blocks, per_group, ppg, c->stream));
+    HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
+    c->step += n;
+    unsigned err = 0;
+    HIPCHK(c, hipMemcpyAsync(&err, bar, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (err) return fail(c, LBM_ESTATE, "lbm_step_persistent: a group barrier timed out (state invalid)");
+    return LBM_OK;
 }
 
 int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap, int32_t ppl, int32_t pipe_major)

@@ -92,6 +92,10 @@ class Pipe:
         self._check(self.lib.lbm_set_launch(self._ctx, int(block), int(zchunk), int(xcd_remap),
                                             int(pipes_per_launch), int(pipe_major)), "lbm_set_launch")
 
+    def step_persistent(self, n: int):
+        """n steps in one persistent cooperative launch (synchronises)."""
+        self._check(self.lib.lbm_step_persistent(self._ctx, int(n)), "lbm_step_persistent")
+
     def stream_copy(self, n: int = 1):
         """n copies of the state with the step's launch geometry (bandwidth ceiling)."""
         self._check(self.lib.lbm_stream_copy(self._ctx, int(n)), "lbm_stream_copy")

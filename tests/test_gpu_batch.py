@@ -84,3 +84,19 @@ def test_set_launch_rejects_bad_values(P):
                 dict(pipe_major=2)):
         with pytest.raises(P.LbmError):
             p.set_launch(**bad)
+
+
+@pytest.mark.parametrize("block,zchunk", [(256, 1), (64, 4)])
+def test_persistent_launch_equals_eager(P, block, zchunk):
+    """One cooperative launch of n steps with a grid barrier between steps
+    gives the same states as n ordinary launches (both buffer parities)."""
+    cfg = _cfg(batch=3)
+    amps = _amps(cfg)
+    ref = P.Pipe(cfg, amps)
+    p = P.Pipe(cfg, amps)
+    p.set_launch(block=block, zchunk=zchunk)
+    for n in (1, 13, 6):
+        ref.step(n)
+        p.step_persistent(n)
+        assert p.step_index == ref.step_index
+        assert np.array_equal(p.populations().cpu().numpy(), ref.populations().cpu().numpy()), n
