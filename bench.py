@@ -73,13 +73,14 @@ def _events(stream):
     return a, b
 
 
-def leg_fp16(steps=500):
+def leg_fp16(steps=500, storage=1, pattern=0):
     """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
     import torch
     import lbm_inputs as LI
     import paper_2405_12082_amd as P
     cfg = LI.preset("turbulent")
-    cfg["storage"] = 1
+    cfg["storage"] = storage
+    cfg["pattern"] = pattern
     amps = LI.preset_amplitudes(cfg)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -100,6 +101,14 @@ def leg_fp16(steps=500):
     return {"value": round(nf / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "ms_per_step": round(ms, 4),
             "bytes_per_update": bpu, "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
             "steps": steps, "state_finite": ok}
+
+
+def leg_aa(steps=500):
+    """The turbulent pipe in FP32 with the AA pattern: one buffer updated in
+    place (half the state memory; same results as two buffers)."""
+    r = leg_fp16(steps, storage=0, pattern=1)
+    r["pattern"] = "AA (in place)"
+    return r
 
 
 def leg_batched(steps=200, graph_k=50):
@@ -279,11 +288,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="turbulent")
     ap.add_argument("--storage", type=int, default=0, help="0: FP32, 1: FP16 deviations")
+    ap.add_argument("--pattern", type=int, default=0, help="0: two buffers, 1: AA in place")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,batched,adjoint,precision",
+    ap.add_argument("--legs", default="fp16,aa,batched,adjoint,precision",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -319,6 +329,7 @@ def main():
         return
     cfg = LI.preset(args.workload)
     cfg["storage"] = args.storage
+    cfg["pattern"] = args.pattern
     cfg["block"] = args.block
     cfg["zchunk"] = args.zchunk
     cfg["xcd_remap"] = args.xcd_remap
@@ -379,7 +390,7 @@ def main():
     kavg_ms = float(np.mean(kern_ms)) if kern_ms else float("nan")
     alg_bytes = nf * cfg["batch"] * bpu
     achieved = alg_bytes / (kavg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage)
+    traffic = measured_traffic(args.workload, args.storage) if args.pattern == 0 else None
     out = {
         "metric": "MLUPS + % HBM roofline (D3Q27 MRT fwd); adjoint/fwd cost ratio",
         "value": round(mlups, 1),
@@ -411,7 +422,7 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     for leg in legs:
-        extra[leg] = {"fp16": leg_fp16, "batched": leg_batched, "adjoint": leg_adjoint,
+        extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "batched": leg_batched, "adjoint": leg_adjoint,
                       "precision": leg_precision}[leg]()
     if extra:
         out["extra"] = extra

@@ -76,7 +76,10 @@ typedef struct {
                              2^k ~ 1/w_i, FP32 collision; 2: FP64 deviations and collision
                              (reference precision, for verification) */
     int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1)) */
-    int32_t pattern;      /* 0: two buffers (A/B) */
+    int32_t pattern;      /* 0: two buffers (A/B); 1: AA, one buffer updated in place (even
+                             steps read and write a node's own slots, odd steps its
+                             neighbours'); same results, half the state memory; no
+                             adjoint (adjoint must be 0) */
     int32_t init;         /* 0: rest (g = 0); 1: log-law mean profile, f = f^eq(1, u_z(r)) */
     double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
     int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state and
@@ -188,7 +191,9 @@ int lbm_profile_read(lbm_ctx *ctx, double *host_out);
 /* Bytes of one saved state (populations, all pipes). */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
 /* Copy the state to / from caller device memory of lbm_state_bytes bytes;
- * lbm_load also sets the step index.  Async, stream-ordered. */
+ * lbm_load also sets the step index.  Async, stream-ordered.  With the AA
+ * pattern the buffer's layout depends on the parity of the step, so a saved
+ * state must be loaded at a step of the same parity. */
 int lbm_save(lbm_ctx *ctx, void *dst, int64_t *step);
 int lbm_load(lbm_ctx *ctx, const void *src, int64_t step);
 
@@ -228,14 +233,16 @@ int lbm_energy_accumulate(lbm_ctx *ctx, double *acc);
  * step s0; no copy when start == ring), then ring[j+1] := one step of
  * ring[j] at step index s0 + j, for j = 0 .. n-2.  ring: device memory for
  * n states, stride bytes apart (stride >= lbm_state_bytes, multiple of 256).
- * The states are exactly those lbm_step would produce.  Async. */
+ * The states are exactly those lbm_step would produce.  Two-buffer pattern
+ * only (LBM_EINVAL otherwise).  Async. */
 int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *ring, size_t stride);
 
 /* Measurement aid: enqueue n copies of the current state buffer into the
  * other buffer with the launch geometry of lbm_step (27 aligned loads and 27
  * non-temporal stores per fluid node, no arithmetic): the practical HBM
  * bandwidth ceiling of the step's access pattern.  Leaves the state
- * unchanged (the copy goes to the spare buffer).  Async. */
+ * unchanged (the copy goes to the spare buffer; with the AA pattern the
+ * buffer is copied onto itself).  Async. */
 int lbm_stream_copy(lbm_ctx *ctx, int32_t n);
 
 /* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */

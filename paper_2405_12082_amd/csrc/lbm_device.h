@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbm_internal.h"
+
 namespace lbm {
 
 // D3Q27 velocities in the appendix order (rest, faces, xy/xz/yz edges, corners).
@@ -138,33 +140,67 @@ __device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, cons
 // Pull streaming, Eq. (streaming): g_i(x, n) = g*_i(x - c_i, n-1) if x - c_i
 // is fluid, else the halfway bounce-back g*_opp(i)(x, n-1) (the Delta = 1/2
 // case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
-// (periodic in z).
-template <typename T, int I>
+// (periodic in z).  FORM_N reads the own slot.
+template <typename T, int I, int FORM>
 __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
 {
-    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    constexpr int d = NSLOT(-cx, -cy);
-    const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
-    typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + I * p.pbytes, zs + p.colo[d]);
-    if constexpr (d != 4) {
-        if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(I) * p.pbytes, zo + p.own);
+    if constexpr (FORM == FORM_N) {
+        return Codec<T>::template ld<I>(p.base + I * p.pbytes, zo + p.own);
+    } else {
+        constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
+        constexpr int d = NSLOT(-cx, -cy);
+        constexpr int here = FORM == FORM_W ? OPP(I) : I;  // physical slot of g*_I
+        const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
+        typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
+        if constexpr (d != 4) {
+            if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
+        }
+        return v;
     }
-    return v;
 }
 
-template <typename T, int I = 0>
+template <typename T, int FORM = FORM_S, int I = 0>
 __device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo,
                                        typename RealOf<T>::type (&g)[27])
 {
-    g[I] = pull_one<T, I>(p, zo, zmo, zpo);
-    if constexpr (I + 1 < 27) gather<T, I + 1>(p, zo, zmo, zpo, g);
+    g[I] = pull_one<T, I, FORM>(p, zo, zmo, zpo);
+    if constexpr (I + 1 < 27) gather<T, FORM, I + 1>(p, zo, zmo, zpo, g);
 }
 
+// two-buffer store: g*_i(x) into slot i of node x of the other buffer
 template <typename T, int I = 0>
 __device__ __forceinline__ void store_all(char *pipe, size_t pbytes, unsigned off, const typename RealOf<T>::type (&g)[27])
 {
     Codec<T>::template st<I>(pipe + I * pbytes, off, g[I]);
     if constexpr (I + 1 < 27) store_all<T, I + 1>(pipe, pbytes, off, g);
+}
+
+// AA pattern, even step: g*_i(x) into slot opp(i) of node x (in place), which
+// leaves the buffer in FORM_W
+template <typename T, int I = 0>
+__device__ __forceinline__ void store_swapped(char *pipe, size_t pbytes, unsigned off,
+                                              const typename RealOf<T>::type (&g)[27])
+{
+    Codec<T>::template st<I>(pipe + OPP(I) * pbytes, off, g[I]);
+    if constexpr (I + 1 < 27) store_swapped<T, I + 1>(pipe, pbytes, off, g);
+}
+
+// AA pattern, odd step: g*_i(x) into slot i of node x + c_i, or, where x + c_i
+// is solid, into slot opp(i) of node x (the bounce-back arrives there as
+// g_opp(i)(x, n+1)); leaves the buffer in FORM_N.  Each location is read and
+// written by the one node that owns it, so the update is race-free in place.
+template <typename T, int I = 0>
+__device__ __forceinline__ void store_push(char *pipe, const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo,
+                                           const typename RealOf<T>::type (&g)[27])
+{
+    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
+    constexpr int d = NSLOT(cx, cy);
+    const unsigned zt = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
+    if (d != 4 && (p.wall & (1u << d)))
+        Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, zo + p.own, g[I]);
+    else
+        Codec<T>::template st<I>(pipe + I * p.pbytes, zt + p.colo[d], g[I]);
+    if constexpr (I + 1 < 27) store_push<T, I + 1>(pipe, p, zo, zmo, zpo, g);
 }
 
 // index of the population with velocity (cx, cy, cz)

@@ -33,6 +33,13 @@ struct Tiles {
     __host__ __device__ long long count() const { return (long long)nkb * nzc; }
 };
 
+// Forms of a population buffer between steps:
+//  FORM_S: slot i of node y holds g*_i(y, n-1), the post-collision value that
+//          node y + c_i pulls (two-buffer pattern);
+//  FORM_W: the same with slots i and opp(i) exchanged (AA pattern, odd n);
+//  FORM_N: slot i of node x holds g_i(x, n) itself (AA pattern, even n).
+enum StateForm : int { FORM_S = 0, FORM_W = 1, FORM_N = 2 };
+
 enum ObserveFlags {
     OBS_MOMENTS = 1,   // dense rho / u outputs
     OBS_POPS = 2,      // dense population deviations
@@ -54,16 +61,20 @@ struct ObserveArgs {
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
+// AA pattern, in place: odd = 0 reads FORM_N and leaves FORM_W, odd = 1 the reverse
+hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf, int odd, int step_off, hipStream_t s);
 // persistent launch: blocks = groups * per_group workgroups, group q owning
-// pipes [q * pipes_per_group, ...); bar: 32 words per group + 32 (error flag)
-hipError_t launch_step_persistent(int storage, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
-                                  unsigned *bar, int blocks, int per_group, int pipes_per_group, hipStream_t s);
-int persistent_blocks_per_cu(int storage, int block);
+// pipes [q * pipes_per_group, ...); bar: 32 words per group + 32 (error
+// flag).  aa: in place in b0, par = parity of the first step.
+hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
+                                  int nsteps, unsigned *bar, int blocks, int per_group, int pipes_per_group,
+                                  hipStream_t s);
+int persistent_blocks_per_cu(int storage, int aa, int block);
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
-hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
+hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
                           int step_off, hipStream_t s);
-hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s);
-hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s);
+hipError_t launch_init(int storage, int form, const Geom &g, const float *u0, void *state, hipStream_t s);
+hipError_t launch_set_pops(int storage, int form, const Geom &g, const float *pops, void *state, hipStream_t s);
 hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
 hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
 hipError_t launch_accumulate_energy(const Geom &g, const Tiles &t, const double *part, double scale, double *acc,

@@ -76,9 +76,14 @@ __device__ __forceinline__ void body_force(const Geom &g, int z, float sig, floa
     }
 }
 
+// Step variants: the two-buffer pattern (read FORM_S from src, aligned store
+// into dst) and the in-place AA pattern (even n: read own slots, store
+// swapped -> FORM_W; odd n: gather FORM_W, push to the neighbours -> FORM_N).
+enum StepMode : int { STEP_AB = 0, STEP_AA_EVEN = 1, STEP_AA_ODD = 2 };
+
 template <typename T>
-__device__ __forceinline__ void collide_store(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px,
-                                              float py, float pq, int z, char *pout, size_t pbytes, unsigned off)
+__device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px, float py,
+                                        float pq, int z)
 {
     using R = typename RealOf<T>::type;
     R ax, ay, az;
@@ -87,15 +92,14 @@ __device__ __forceinline__ void collide_store(const Geom &g, typename RealOf<T>:
     R ux, uy, uz;
     const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, R(g.omega), ux, uy, uz);
     post_collision_all<R>(c, v);
-    store_all<T>(pout, pbytes, off, v);
 }
 
-// One tile of one time step (column k of the tile, its z planes): pull
-// gather (streaming + bounce-back) of g(n) from S^T g(n), collision at
-// a(x, n), aligned store of g*(n).
-template <typename T>
-__device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *__restrict__ src,
-                                          T *__restrict__ dst, long long n)
+// One tile of one time step (column k of the tile, its z planes): gather of
+// g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
+// For the AA modes src and dst are the same buffer.
+template <typename T, int MODE>
+__device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *src, T *dst,
+                                          long long n)
 {
     const int k = tc.k;
     const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
@@ -106,11 +110,19 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const int z0 = tc.zc * t.zchunk;
     const int z1 = min(z0 + t.zchunk, g.nz);
+    constexpr int FORM = MODE == STEP_AB ? FORM_S : (MODE == STEP_AA_EVEN ? FORM_N : FORM_W);
     for (int z = z0; z < z1; ++z) {
         const unsigned zo = (unsigned)z * rowb;
+        const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
         typename RealOf<T>::type v[27];
-        gather<T>(p, zo, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
-        collide_store<T>(g, v, sig, px, py, pq, z, pout, p.pbytes, zo + p.own);
+        gather<T, FORM>(p, zo, zmo, zpo, v);
+        collide<T>(g, v, sig, px, py, pq, z);
+        if constexpr (MODE == STEP_AB)
+            store_all<T>(pout, p.pbytes, zo + p.own, v);
+        else if constexpr (MODE == STEP_AA_EVEN)
+            store_swapped<T>(pout, p.pbytes, zo + p.own, v);
+        else
+            store_push<T>(pout, p, zo, zmo, zpo, v);
     }
 }
 
@@ -120,7 +132,17 @@ __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, cons
 {
     const TileCoord tc = decode_tile(t, BLOCK);
     if (tc.k >= g.ncol) return;
-    step_tile<T>(g, t, tc, src, dst, *g.step_dev + step_off);
+    step_tile<T, STEP_AB>(g, t, tc, src, dst, *g.step_dev + step_off);
+}
+
+// AA pattern: one buffer, updated in place (no __restrict__: reads and
+// writes share it)
+template <typename T, int BLOCK, int MODE>
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step_aa(const Geom g, const Tiles t, T *buf, int step_off)
+{
+    const TileCoord tc = decode_tile(t, BLOCK);
+    if (tc.k >= g.ncol) return;
+    step_tile<T, MODE>(g, t, tc, buf, buf, *g.step_dev + step_off);
 }
 
 // Barrier of one group of workgroups inside a cooperative launch (all
@@ -174,9 +196,10 @@ __device__ __forceinline__ bool group_barrier(unsigned *gb, unsigned *err, unsig
 // group's counter (dynamic balance: a slower CU takes fewer tiles; the next
 // ticket is requested before the current tiles run, hiding the atomic's
 // latency), then meet at the group barrier before the next step.  Buffers
-// alternate: step j reads buf[(par + j) & 1].
+// alternate: step j reads buf[(par + j) & 1].  AA pattern: one buffer
+// (buf0), par is the parity of the first step.
 constexpr int PERSIST_CHUNK = 2;
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool AA>
 __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const Tiles t, T *buf0, T *buf1, int par,
                                                            int nsteps, unsigned *bar, int per_group,
                                                            int pipes_per_group)
@@ -203,7 +226,15 @@ __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const T
             const int lo = cur * PERSIST_CHUNK, hi = min(lo + PERSIST_CHUNK, ntiles);
             for (int tile = lo; tile < hi; ++tile) {
                 const TileCoord tc = tile_coord(t, first + tile, BLOCK);
-                if (tc.k < g.ncol) step_tile<T>(g, t, tc, src, dst, n0 + j);
+                if (tc.k >= g.ncol) continue;
+                if constexpr (AA) {
+                    if ((par + j) & 1)
+                        step_tile<T, STEP_AA_ODD>(g, t, tc, buf0, buf0, n0 + j);
+                    else
+                        step_tile<T, STEP_AA_EVEN>(g, t, tc, buf0, buf0, n0 + j);
+                } else {
+                    step_tile<T, STEP_AB>(g, t, tc, src, dst, n0 + j);
+                }
             }
             if (threadIdx.x == 0) ticket = nxt;
             __syncthreads();
@@ -264,7 +295,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [BLOCK
             for (int q = 0; q < NV; ++q) v[q] += lds[w * NV + q];
 }
 
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int FORM>
 __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, const T *__restrict__ state,
                                                     const ObserveArgs o, int step_off)
 {
@@ -290,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
         using R = typename RealOf<T>::type;
         for (int z = z0; z < z1; ++z) {
             R v[27];
-            gather<T>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
+            gather<T, FORM>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
             R ax, ay, az;
             body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
             const Moments<R> m = moments_of<R>(v);
@@ -423,29 +454,56 @@ __global__ __launch_bounds__(256) void k_reduce_profile(const double *__restrict
 }
 
 // ---------------------------------------------------------------- state writers
-// The buffer holds S^T g: slot j of node y is g_j(y + c_j) when y + c_j is
-// fluid, else g_opp(j)(y) (inverse of the bounce-back pull).
-template <typename T, int J = 0>
-__device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&col)[9], const float *u0, int k,
-                                           int z, const Axis<typename RealOf<T>::type> &zero,
-                                           const Axis<typename RealOf<T>::type> &own)
+// Writers of a state g in a buffer form: FORM_S stores in slot j of node y
+// the value g_j(y + c_j) when y + c_j is fluid, else g_opp(j)(y) (inverse of
+// the bounce-back pull); FORM_W the same with slots j and opp(j) exchanged;
+// FORM_N stores g_j(y) in slot j.
+template <int FORM, int J>
+__device__ __forceinline__ void writer_source(const int (&col)[9], int k, int &src_col, int &src_dir, int &dz)
 {
-    using R = typename RealOf<T>::type;
-    constexpr int cx = CX(J), cy = CY(J);
-    const int sc = col[NSLOT(cx, cy)];
-    R v;
-    if (sc >= 0) {
-        const Axis<R> a = axis_factors(R(u0[sc]));
-        v = feq_dev<J, R>(R(0), zero, zero, a);
+    if constexpr (FORM == FORM_N) {
+        src_col = k;
+        src_dir = J;
+        dz = 0;
     } else {
-        v = feq_dev<OPP(J), R>(R(0), zero, zero, own);
+        constexpr int j = FORM == FORM_W ? OPP(J) : J;  // S-form slot stored in physical slot J
+        const int sc = col[NSLOT(CX(j), CY(j))];
+        if (sc >= 0) {
+            src_col = sc;
+            src_dir = j;
+            dz = CZ(j);
+        } else {
+            src_col = k;
+            src_dir = OPP(j);
+            dz = 0;
+        }
     }
-    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
-    if constexpr (J + 1 < 27) init_slots<T, J + 1>(pipe, g, col, u0, k, z, zero, own);
 }
 
-// Initial state f^0 = f^eq(1, (0, 0, u0(r))) (u0 = 0: rest)
-template <typename T>
+__device__ __forceinline__ int wrap_z(int z, int dz, int nz) { return dz == 0 ? z : (dz > 0 ? wrap_p(z, nz) : wrap_m(z, nz)); }
+
+// initial state f = f^eq(1, (0, 0, u0(r))): g_j depends only on the column
+template <typename T, int FORM, int J = 0>
+__device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&col)[9], const float *u0, int k,
+                                           int z, const Axis<typename RealOf<T>::type> &zero)
+{
+    using R = typename RealOf<T>::type;
+    R v;
+    if constexpr (FORM == FORM_N) {
+        v = feq_dev<J, R>(R(0), zero, zero, axis_factors(R(u0[k])));
+    } else {
+        constexpr int j = FORM == FORM_W ? OPP(J) : J;  // S-form slot stored in physical slot J
+        const int sc = col[NSLOT(CX(j), CY(j))];
+        if (sc >= 0)
+            v = feq_dev<j, R>(R(0), zero, zero, axis_factors(R(u0[sc])));
+        else
+            v = feq_dev<OPP(j), R>(R(0), zero, zero, axis_factors(R(u0[k])));
+    }
+    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
+    if constexpr (J + 1 < 27) init_slots<T, FORM, J + 1>(pipe, g, col, u0, k, z, zero);
+}
+
+template <typename T, int FORM>
 __global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restrict__ u0, T *__restrict__ state)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -457,30 +515,24 @@ __global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restr
     int col[9];
     load_columns(g, k, col);
     using R = typename RealOf<T>::type;
-    const Axis<R> zero = axis_factors(R(0)), own = axis_factors(R(u0[k]));
-    init_slots<T>(state + (size_t)b * g.pipe, g, col, u0, k, z, zero, own);
+    const Axis<R> zero = axis_factors(R(0));
+    init_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, u0, k, z, zero);
 }
 
-template <typename T, int J = 0>
+template <typename T, int FORM, int J = 0>
 __device__ __forceinline__ void set_slots(T *pipe, const Geom &g, const int (&col)[9], const float *src, int k, int z,
                                           size_t plane, size_t popstride)
 {
-    constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
-    const int sc = col[NSLOT(cx, cy)];
-    float v;
-    if (sc >= 0) {
-        const unsigned xy = g.colxy[sc];
-        const int zs = cz == 0 ? z : (cz > 0 ? (z == g.nz - 1 ? 0 : z + 1) : (z == 0 ? g.nz - 1 : z - 1));
-        v = src[J * popstride + (size_t)zs * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
-    } else {
-        const unsigned xy = g.colxy[k];
-        v = src[OPP(J) * popstride + (size_t)z * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
-    }
+    int sc, dir, dz;
+    writer_source<FORM, J>(col, k, sc, dir, dz);
+    const unsigned xy = g.colxy[sc];
+    const int zs = wrap_z(z, dz, g.nz);
+    const float v = src[dir * popstride + (size_t)zs * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
     Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
-    if constexpr (J + 1 < 27) set_slots<T, J + 1>(pipe, g, col, src, k, z, plane, popstride);
+    if constexpr (J + 1 < 27) set_slots<T, FORM, J + 1>(pipe, g, col, src, k, z, plane, popstride);
 }
 
-template <typename T>
+template <typename T, int FORM>
 __global__ __launch_bounds__(256) void k_set_pops(const Geom g, const float *__restrict__ pops, T *__restrict__ state)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -492,7 +544,7 @@ __global__ __launch_bounds__(256) void k_set_pops(const Geom g, const float *__r
     int col[9];
     load_columns(g, k, col);
     const size_t plane = (size_t)g.nx * g.ny, popstride = (size_t)g.nz * plane;
-    set_slots<T>(state + (size_t)b * g.pipe, g, col, pops + (size_t)b * 27 * popstride, k, z, plane, popstride);
+    set_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, pops + (size_t)b * 27 * popstride, k, z, plane, popstride);
 }
 
 __global__ void k_fill(uint32_t *p, size_t n)
@@ -537,7 +589,33 @@ hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const 
     return hipGetLastError();
 }
 
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int MODE>
+static void step_aa_t(const Geom &g, const Tiles &t, void *buf, int off, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step_aa<T, BLOCK, MODE>), dim3(grid_of(t)), dim3(BLOCK), 0, s, g, t, (T *)buf, off);
+}
+template <typename T, int MODE>
+static hipError_t step_aa_block(const Geom &g, const Tiles &t, void *buf, int off, hipStream_t s)
+{
+    switch (t.block) {
+    case 64: step_aa_t<T, 64, MODE>(g, t, buf, off, s); break;
+    case 128: step_aa_t<T, 128, MODE>(g, t, buf, off, s); break;
+    default: step_aa_t<T, 256, MODE>(g, t, buf, off, s); break;
+    }
+    return hipGetLastError();
+}
+template <typename T>
+static hipError_t step_aa_mode(const Geom &g, const Tiles &t, void *buf, int odd, int off, hipStream_t s)
+{
+    return odd ? step_aa_block<T, STEP_AA_ODD>(g, t, buf, off, s) : step_aa_block<T, STEP_AA_EVEN>(g, t, buf, off, s);
+}
+hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf, int odd, int off, hipStream_t s)
+{
+    if (storage == 2) return step_aa_mode<double>(g, t, buf, odd, off, s);
+    return storage == 1 ? step_aa_mode<__half>(g, t, buf, odd, off, s) : step_aa_mode<float>(g, t, buf, odd, off, s);
+}
+
+template <typename T, int BLOCK, bool AA>
 static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
                                int blocks, int per_group, int ppg, hipStream_t s)
 {
@@ -545,46 +623,59 @@ static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1
     Tiles tt = t;
     T *p0 = (T *)b0, *p1 = (T *)b1;
     void *args[] = {&gg, &tt, &p0, &p1, &par, &nsteps, &bar, &per_group, &ppg};
-    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK>;
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK, AA>;
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
 }
 
-template <typename T>
+template <typename T, bool AA>
 static hipError_t persistent_block(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
                                    int blocks, int per_group, int ppg, hipStream_t s)
 {
     switch (t.block) {
-    case 64: return persistent_t<T, 64>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    case 128: return persistent_t<T, 128>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    default: return persistent_t<T, 256>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 64: return persistent_t<T, 64, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 128: return persistent_t<T, 128, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    default: return persistent_t<T, 256, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
     }
 }
-
-hipError_t launch_step_persistent(int storage, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
-                                  unsigned *bar, int blocks, int per_group, int pipes_per_group, hipStream_t s)
+template <typename T>
+static hipError_t persistent_pattern(int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
+                                     unsigned *bar, int blocks, int per_group, int ppg, hipStream_t s)
 {
-    if (storage == 2)
-        return persistent_block<double>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
-    if (storage == 1)
-        return persistent_block<__half>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
-    return persistent_block<float>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+    return aa ? persistent_block<T, true>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s)
+              : persistent_block<T, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
 }
 
-template <typename T, int BLOCK> static int occ_t()
+hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
+                                  int nsteps, unsigned *bar, int blocks, int per_group, int pipes_per_group,
+                                  hipStream_t s)
+{
+    if (storage == 2)
+        return persistent_pattern<double>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+    if (storage == 1)
+        return persistent_pattern<__half>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+    return persistent_pattern<float>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+}
+
+template <typename T, int BLOCK, bool AA> static int occ_t()
 {
     int n = 0;
-    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK>;
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK, AA>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(fn), BLOCK, 0) != hipSuccess)
         return 0;
     return n;
 }
-template <typename T> static int occ_block(int block)
+template <typename T, bool AA> static int occ_block(int block)
 {
-    return block == 64 ? occ_t<T, 64>() : (block == 128 ? occ_t<T, 128>() : occ_t<T, 256>());
+    return block == 64 ? occ_t<T, 64, AA>() : (block == 128 ? occ_t<T, 128, AA>() : occ_t<T, 256, AA>());
 }
-int persistent_blocks_per_cu(int storage, int block)
+template <typename T> static int occ_pattern(int aa, int block)
 {
-    return storage == 2 ? occ_block<double>(block) : (storage == 1 ? occ_block<__half>(block) : occ_block<float>(block));
+    return aa ? occ_block<T, true>(block) : occ_block<T, false>(block);
+}
+int persistent_blocks_per_cu(int storage, int aa, int block)
+{
+    return storage == 2 ? occ_pattern<double>(aa, block)
+                        : (storage == 1 ? occ_pattern<__half>(aa, block) : occ_pattern<float>(aa, block));
 }
 
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
@@ -593,16 +684,31 @@ hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *s
     return storage == 1 ? step_t<__half>(g, t, src, dst, off, s) : step_t<float>(g, t, src, dst, off, s);
 }
 
-hipError_t launch_observe(int storage, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off,
-                          hipStream_t s)
+template <typename T, int FORM>
+static void observe_t(const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off, hipStream_t s)
 {
-    const dim3 grid(grid_of(t));
-    if (storage == 2)
-        hipLaunchKernelGGL((k_observe<double, 256>), grid, dim3(256), 0, s, g, t, (const double *)state, o, off);
-    else if (storage == 1)
-        hipLaunchKernelGGL((k_observe<__half, 256>), grid, dim3(256), 0, s, g, t, (const __half *)state, o, off);
+    hipLaunchKernelGGL((k_observe<T, 256, FORM>), dim3(grid_of(t)), dim3(256), 0, s, g, t, (const T *)state, o, off);
+}
+template <typename T>
+static void observe_form(int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off,
+                         hipStream_t s)
+{
+    if (form == FORM_N)
+        observe_t<T, FORM_N>(g, t, state, o, off, s);
+    else if (form == FORM_W)
+        observe_t<T, FORM_W>(g, t, state, o, off, s);
     else
-        hipLaunchKernelGGL((k_observe<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)state, o, off);
+        observe_t<T, FORM_S>(g, t, state, o, off, s);
+}
+hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
+                          int off, hipStream_t s)
+{
+    if (storage == 2)
+        observe_form<double>(form, g, t, state, o, off, s);
+    else if (storage == 1)
+        observe_form<__half>(form, g, t, state, o, off, s);
+    else
+        observe_form<float>(form, g, t, state, o, off, s);
     return hipGetLastError();
 }
 
@@ -612,25 +718,45 @@ static dim3 node_grid(const Geom &g)
     return dim3((unsigned)((total + 255) / 256));
 }
 
-hipError_t launch_init(int storage, const Geom &g, const float *u0, void *state, hipStream_t s)
+template <typename T>
+static void init_form(int form, const Geom &g, const float *u0, void *state, hipStream_t s)
+{
+    if (form == FORM_N)
+        hipLaunchKernelGGL((k_init<T, FORM_N>), node_grid(g), dim3(256), 0, s, g, u0, (T *)state);
+    else if (form == FORM_W)
+        hipLaunchKernelGGL((k_init<T, FORM_W>), node_grid(g), dim3(256), 0, s, g, u0, (T *)state);
+    else
+        hipLaunchKernelGGL((k_init<T, FORM_S>), node_grid(g), dim3(256), 0, s, g, u0, (T *)state);
+}
+hipError_t launch_init(int storage, int form, const Geom &g, const float *u0, void *state, hipStream_t s)
 {
     if (storage == 2)
-        hipLaunchKernelGGL((k_init<double>), node_grid(g), dim3(256), 0, s, g, u0, (double *)state);
+        init_form<double>(form, g, u0, state, s);
     else if (storage == 1)
-        hipLaunchKernelGGL((k_init<__half>), node_grid(g), dim3(256), 0, s, g, u0, (__half *)state);
+        init_form<__half>(form, g, u0, state, s);
     else
-        hipLaunchKernelGGL((k_init<float>), node_grid(g), dim3(256), 0, s, g, u0, (float *)state);
+        init_form<float>(form, g, u0, state, s);
     return hipGetLastError();
 }
 
-hipError_t launch_set_pops(int storage, const Geom &g, const float *pops, void *state, hipStream_t s)
+template <typename T>
+static void set_pops_form(int form, const Geom &g, const float *pops, void *state, hipStream_t s)
+{
+    if (form == FORM_N)
+        hipLaunchKernelGGL((k_set_pops<T, FORM_N>), node_grid(g), dim3(256), 0, s, g, pops, (T *)state);
+    else if (form == FORM_W)
+        hipLaunchKernelGGL((k_set_pops<T, FORM_W>), node_grid(g), dim3(256), 0, s, g, pops, (T *)state);
+    else
+        hipLaunchKernelGGL((k_set_pops<T, FORM_S>), node_grid(g), dim3(256), 0, s, g, pops, (T *)state);
+}
+hipError_t launch_set_pops(int storage, int form, const Geom &g, const float *pops, void *state, hipStream_t s)
 {
     if (storage == 2)
-        hipLaunchKernelGGL((k_set_pops<double>), node_grid(g), dim3(256), 0, s, g, pops, (double *)state);
+        set_pops_form<double>(form, g, pops, state, s);
     else if (storage == 1)
-        hipLaunchKernelGGL((k_set_pops<__half>), node_grid(g), dim3(256), 0, s, g, pops, (__half *)state);
+        set_pops_form<__half>(form, g, pops, state, s);
     else
-        hipLaunchKernelGGL((k_set_pops<float>), node_grid(g), dim3(256), 0, s, g, pops, (float *)state);
+        set_pops_form<float>(form, g, pops, state, s);
     return hipGetLastError();
 }
 

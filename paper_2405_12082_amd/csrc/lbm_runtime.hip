@@ -81,7 +81,8 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.storage < 0 || c.storage > 2) return bad("storage must be 0 (FP32), 1 (FP16) or 2 (FP64)");
     if (c.storage == 2 && c.adjoint == 1) return bad("the adjoint of the FP64 forward is FP64 (adjoint = 2)");
     if (c.wall != 0) return bad("wall must be 0 (halfway bounce-back)");
-    if (c.pattern != 0) return bad("pattern must be 0 (two buffers)");
+    if (c.pattern != 0 && c.pattern != 1) return bad("pattern must be 0 (two buffers) or 1 (AA, in place)");
+    if (c.pattern == 1 && c.adjoint != 0) return bad("the adjoint needs the two-buffer pattern (pattern = 0)");
     if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");
     if (c.adjoint < 0 || c.adjoint > 2) return bad("adjoint must be 0 (none), 1 (FP32) or 2 (FP64)");
     if (c.init == 1 && (c.radius <= 0.0 || !(c.u_tau >= 0.0))) return bad("log-law init needs radius > 0, u_tau >= 0");
@@ -126,7 +127,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     };
     const size_t B = (size_t)c.batch, P = (size_t)L.P;
     L.off_state[0] = take(L.state_bytes);
-    L.off_state[1] = take(L.state_bytes);
+    L.off_state[1] = c.pattern == 1 ? L.off_state[0] : take(L.state_bytes);  // AA: one buffer
     L.off_nbr = take(9 * P * sizeof(int));
     L.off_colxy = take(P * sizeof(unsigned));
     L.off_fshape = take(B * 3 * P * sizeof(float));
@@ -208,6 +209,8 @@ struct lbm_ctx {
     bool lam_nonzero = false;
 
     void *state(long long n) const { return ws + L.off_state[n & 1]; }
+    // form of the buffer that holds the state of step n
+    int form(long long n) const { return cfg.pattern == 1 ? ((n & 1) ? FORM_W : FORM_N) : FORM_S; }
 };
 
 namespace {
@@ -243,6 +246,8 @@ hipError_t launch_steps(lbm_ctx *c, long long first, int n, hipStream_t s)
         Tiles t = c->L.step;
         t.b0 = b0;
         t.nb = std::min(c->ppl, B - b0);
+        if (c->cfg.pattern == 1)
+            return launch_step_aa(c->cfg.storage, c->geom, t, c->state(first + j), (int)((first + j) & 1), j, s);
         return launch_step(c->cfg.storage, c->geom, t, c->state(first + j), c->state(first + j + 1), j, s);
     };
     hipError_t e = hipSuccess;
@@ -266,7 +271,7 @@ int do_step_eager(lbm_ctx *c, int n)
 
 int observe(lbm_ctx *c, const ObserveArgs &o)
 {
-    HIPCHK(c, launch_observe(c->cfg.storage, c->geom, c->L.obs, c->state(c->step), o, 0, c->stream));
+    HIPCHK(c, launch_observe(c->cfg.storage, c->form(c->step), c->geom, c->L.obs, c->state(c->step), o, 0, c->stream));
     return LBM_OK;
 }
 
@@ -410,9 +415,9 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_state[0], L.state_bytes, c->stream);  // padding reads as 0
-    if (e == hipSuccess) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
+    if (e == hipSuccess && L.off_state[1] != L.off_state[0]) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_prof_acc, B * P * 5 * sizeof(double), c->stream);
-    if (e == hipSuccess) e = launch_init(g.storage, G, (const float *)(ws + L.off_u0), c->state(0), c->stream);
+    if (e == hipSuccess) e = launch_init(g.storage, c->form(0), G, (const float *)(ws + L.off_u0), c->state(0), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
@@ -475,7 +480,8 @@ int lbm_step_persistent(lbm_ctx *c, int32_t n)
     int dev = 0, cus = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, c->L.step.block);
+    const int aa = c->cfg.pattern == 1;
+    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, aa, c->L.step.block);
     if (per_cu < 1 || cus < 1) return fail(c, LBM_EHIP, "lbm_step_persistent: occupancy query failed");
     Tiles t = c->L.step;
     t.b0 = 0;
@@ -491,7 +497,8 @@ int lbm_step_persistent(lbm_ctx *c, int32_t n)
     const int blocks = groups * per_group;
     unsigned *bar = (unsigned *)(c->ws + c->L.off_bar);
     HIPCHK(c, launch_fill(bar, 32 * sizeof(unsigned) * ((size_t)groups + 1), c->stream));
-    HIPCHK(c, launch_step_persistent(c->cfg.storage, c->geom, t, c->state(c->step), c->state(c->step + 1), 0, n, bar,
+    HIPCHK(c, launch_step_persistent(c->cfg.storage, aa, c->geom, t, c->state(c->step), c->state(c->step + 1),
+                                     aa ? (int)(c->step & 1) : 0, n, bar,
                                      blocks, per_group, ppg, c->stream));
     HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
     c->step += n;
@@ -584,7 +591,7 @@ int lbm_set_populations(lbm_ctx *c, const float *g, int64_t step)
     CHECK_CTX(c);
     if (!g || step < 0) return fail(c, LBM_EINVAL, "lbm_set_populations: NULL input or negative step");
     c->step = step;
-    HIPCHK(c, launch_set_pops(c->cfg.storage, c->geom, g, c->state(step), c->stream));
+    HIPCHK(c, launch_set_pops(c->cfg.storage, c->form(step), c->geom, g, c->state(step), c->stream));
     HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
     return LBM_OK;
 }
@@ -644,6 +651,7 @@ int lbm_recompute(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *ri
 {
     CHECK_CTX(c);
     if (!start || !ring || n < 1 || s0 < 0) return fail(c, LBM_EINVAL, "lbm_recompute: bad arguments");
+    if (c->cfg.pattern != 0) return fail(c, LBM_EINVAL, "lbm_recompute needs the two-buffer pattern");
     if (stride < c->L.state_bytes || (stride & 255) || ((uintptr_t)ring & 255))
         return fail(c, LBM_EINVAL, "lbm_recompute: stride must be >= the state size and ring/stride 256-byte aligned");
     char *r = (char *)ring;

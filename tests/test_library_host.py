@@ -52,7 +52,8 @@ def test_fp16_storage_halves_the_state():
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(batch=0), dict(tau=0.5), dict(tau=0.4), dict(n_modes=7), dict(n_modes=-1),
-    dict(storage=3), dict(storage=2, adjoint=1), dict(adjoint=3), dict(wall=1), dict(pattern=1),
+    dict(storage=3), dict(storage=2, adjoint=1), dict(adjoint=3), dict(wall=1), dict(pattern=2),
+    dict(pattern=1, adjoint=1),
     dict(init=2), dict(radius=12.0),
     dict(block=96), dict(zchunk=65), dict(n_modes=2, period=0.0), dict(radius=0.4),
 ])
@@ -84,6 +85,15 @@ def test_workspace_grows_with_adjoint_buffers():
     cfg["adjoint"] = 1
     b = P.describe(P.make_config(**cfg)).workspace_bytes
     assert b - a >= 2 * 4 * 27 * 384 * 6400
+
+
+def test_aa_pattern_keeps_one_state_buffer():
+    cfg = LI.preset("turbulent")
+    ab = P.describe(P.make_config(**cfg))
+    cfg["pattern"] = 1
+    aa = P.describe(P.make_config(**cfg))
+    assert aa.state_bytes == ab.state_bytes and aa.bytes_per_update == ab.bytes_per_update
+    assert ab.workspace_bytes - aa.workspace_bytes == ab.state_bytes
 
 
 def test_periodic_box_layout():
