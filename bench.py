@@ -124,8 +124,10 @@ def leg_batched(steps=200, graph_k=50):
     B = cfg["batch"]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        p = P.Pipe(cfg, amps, stream=stream)
-        tune = autotune.autotune(p, steps=10)
+        # launch geometry and buffer pattern (two buffers / AA in place)
+        tune = autotune.choose_pattern(cfg, amps, steps=10, stream=stream)
+        p = P.Pipe(dict(cfg, pattern=tune["pattern"]), amps, stream=stream)
+        p.set_launch(**tune["best"])
         p.step_graph(2 * graph_k, graph_k)  # capture + warm
         a, b = _events(stream)
         a.record(stream)
@@ -161,7 +163,9 @@ def leg_batched(steps=200, graph_k=50):
         torch.cuda.empty_cache()
     return {"value": round(B * nf / (ms_batched * 1e-3) / 1e6, 1), "unit": "MLUPS (aggregate)",
             "ms_per_step": round(ms_batched, 4), "pipes": B, "fluid_nodes_per_pipe": nf,
-            "launch": tune["best"], "graph_steps": graph_k, "autotune_cached": tune["cached"],
+            "launch": tune["best"], "pattern": ["two buffers", "AA"][tune["pattern"]],
+            "autotune_ms_by_pattern": {["two buffers", "AA"][q]: round(v, 4) for q, v in tune["by_pattern"].items()},
+            "graph_steps": graph_k, "autotune_cached": tune["cached"],
             "sequential_single_pipes": {"value": round(B * nf / (ms_seq * 1e-3) / 1e6, 1),
                                         "ms_per_step": round(ms_seq, 4)},
             "speedup_vs_sequential": round(ms_seq / ms_batched, 3),

@@ -1,11 +1,14 @@
 """Launch-geometry autotuner for the fused step.
 
 Exhaustive search over (threads per block, z planes per thread, tile order,
-pipes per launch) on a live context: each candidate is set with
+pipes per launch, step order) on a live context: each candidate is set with
 ``lbm_set_launch`` and timed over a few steps with HIP events on the pipe's
 stream.  The state is saved before and restored after the search, so tuning
 does not advance the simulation.  Results are cached in a JSON file keyed by
-the pipe shape, batch, storage and GPU architecture.
+the pipe shape, batch, storage, buffer pattern and GPU architecture.
+:func:`choose_pattern` tunes the two-buffer and the AA pattern of a
+configuration and returns the faster (the pattern is fixed when a context is
+created, so this builds one context per pattern).
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbm_mi355x", "a
 def _key(pipe) -> str:
     c = pipe.cfg
     arch = torch.cuda.get_device_properties(pipe.device).gcnArchName.split(":")[0]
-    return f"{arch}|{c.nx}x{c.ny}x{c.nz}|R{c.radius:g}|B{c.batch}|s{c.storage}"
+    return f"{arch}|{c.nx}x{c.ny}x{c.nz}|R{c.radius:g}|B{c.batch}|s{c.storage}|p{c.pattern}"
 
 
 def candidates(batch: int):
@@ -83,3 +86,23 @@ def autotune(pipe, steps: int = 10, cache_path: str | None = DEFAULT_CACHE, forc
             json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, cache_path)
     return dict(rec, cached=False)
+
+
+def choose_pattern(cfg: dict, amps, steps: int = 10, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+                   device="cuda", stream=None) -> dict:
+    """Autotune the two-buffer (0) and the AA (1) pattern of ``cfg`` and
+    return the faster: {"pattern", "best" (launch geometry), "ms_per_step",
+    "by_pattern": {pattern: ms_per_step}, "cached"}.  Configurations with
+    adjoint buffers allow only the two-buffer pattern."""
+    from .pipe import Pipe
+    patterns = (0,) if cfg.get("adjoint", 0) else (0, 1)
+    res = {}
+    for pat in patterns:
+        p = Pipe(dict(cfg, pattern=pat), amps, device=device, stream=stream)
+        res[pat] = autotune(p, steps, cache_path, force)
+        del p
+        torch.cuda.empty_cache()
+    pat = min(res, key=lambda q: res[q]["ms_per_step"])
+    return {"pattern": pat, "best": res[pat]["best"], "ms_per_step": res[pat]["ms_per_step"],
+            "by_pattern": {q: res[q]["ms_per_step"] for q in res},
+            "cached": all(r["cached"] for r in res.values())}

@@ -100,3 +100,19 @@ def test_persistent_launch_equals_eager(P, block, zchunk):
         p.step_persistent(n)
         assert p.step_index == ref.step_index
         assert np.array_equal(p.populations().cpu().numpy(), ref.populations().cpu().numpy()), n
+
+
+def test_choose_pattern_tunes_both_patterns(P, tmp_path):
+    from paper_2405_12082_amd import autotune
+    cfg = _cfg(batch=2)
+    amps = _amps(cfg)
+    cache = os.path.join(tmp_path, "tune.json")
+    r = autotune.choose_pattern(cfg, amps, steps=2, cache_path=cache)
+    _log(f"choose_pattern: {r}")
+    assert r["pattern"] in (0, 1) and set(r["by_pattern"]) == {0, 1} and not r["cached"]
+    assert r["ms_per_step"] == min(r["by_pattern"].values())
+    r2 = autotune.choose_pattern(cfg, amps, cache_path=cache)
+    assert r2["cached"] and r2["pattern"] == r["pattern"] and r2["best"] == r["best"]
+    # the adjoint needs two buffers
+    r3 = autotune.choose_pattern(dict(cfg, adjoint=1), amps, steps=2, cache_path=cache)
+    assert r3["pattern"] == 0 and set(r3["by_pattern"]) == {0}
