@@ -75,7 +75,10 @@ typedef struct {
     int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations scaled by
                              2^k ~ 1/w_i, FP32 collision; 2: FP64 deviations and collision
                              (reference precision, for verification) */
-    int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1)) */
+    int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1));
+                             1: interpolated wall of Eqs. (fbc1)/(fbc2) with the exact
+                             fraction Delta of each cut link at r = R (two-buffer
+                             pattern, no adjoint) */
     int32_t pattern;      /* 0: two buffers (A/B); 1: AA, one buffer updated in place (even
                              steps read and write a node's own slots, odd steps its
                              neighbours'); same results, half the state memory; no

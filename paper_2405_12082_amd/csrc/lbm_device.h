@@ -111,22 +111,28 @@ template <> struct Codec<__half> {
 // ---------------------------------------------------------------- gather
 // Per-thread view of one pipe's population buffer for one column k:
 // byte offsets of the 9 in-plane neighbour columns (own column where the
-// neighbour is solid) and a bit mask of the solid ones.
+// neighbour is solid), a bit mask of the solid ones, and (interpolated wall
+// only) the column's wall coefficients.
 template <typename T> struct Pull {
     const char *base;   // pipe base
     size_t pbytes;      // bytes between populations (nz * P * sizeof(T))
     unsigned colo[9];   // byte offset of the column in slot d within a plane
     unsigned wall;      // bit d set: slot d is solid
     unsigned own;       // byte offset of column k within a plane
+    const double *bc;   // interpolated wall: coefficient of slot d at bc[d * P]; null: bounce-back
+    int P;
 };
 
 template <typename T>
-__device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k)
+__device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k,
+                                             const double *bcoef = nullptr)
 {
     Pull<T> p;
     p.base = reinterpret_cast<const char *>(pipe);
     p.pbytes = pstride * sizeof(T);
     p.own = (unsigned)k * sizeof(T);
+    p.bc = bcoef ? bcoef + k : nullptr;
+    p.P = P;
     p.wall = 0;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
@@ -138,10 +144,15 @@ __device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, cons
 }
 
 // Pull streaming, Eq. (streaming): g_i(x, n) = g*_i(x - c_i, n-1) if x - c_i
-// is fluid, else the halfway bounce-back g*_opp(i)(x, n-1) (the Delta = 1/2
-// case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
-// (periodic in z).  FORM_N reads the own slot.
-template <typename T, int I, int FORM>
+// is fluid.  Else the wall: halfway bounce-back g*_opp(i)(x, n-1) (the
+// Delta = 1/2 case of Eq. (fbc1)), or, with the interpolated wall of Eqs.
+// (fbc1)/(fbc2), c g*_opp(i)(x) + (1 - c) X with the column's coefficient
+// cf = +-c for the link: cf > 0 (Delta >= 1/2, c = 1/(2 Delta)): X =
+// g*_i(x); cf < 0 (Delta < 1/2 and x + c_i fluid, c = 2 Delta): X =
+// g*_opp(i)(x + c_i); cf = 1: bounce-back.  (Deviations g = f - w combine
+// like f: the weights sum to 1 and w_i = w_opp(i).)  zo/zmo/zpo: byte
+// offsets of planes z, z-1, z+1 (periodic in z).  FORM_N reads the own slot.
+template <typename T, int I, int FORM, bool WALL>
 __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
 {
     if constexpr (FORM == FORM_N) {
@@ -151,20 +162,36 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, u
         constexpr int d = NSLOT(-cx, -cy);
         constexpr int here = FORM == FORM_W ? OPP(I) : I;  // physical slot of g*_I
         const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
-        typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
+        using R = typename RealOf<T>::type;
+        R v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
         if constexpr (d != 4) {
-            if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
+            if (p.wall & (1u << d)) {
+                v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
+                if constexpr (WALL) {
+                    const double cf = p.bc[d * p.P];
+                    if (cf != 1.0) {
+                        const R c = R(cf > 0.0 ? cf : -cf);
+                        constexpr int dff = 8 - d;  // slot of x + c_i
+                        const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
+                        const R x = cf > 0.0 ? Codec<T>::template ld<I>(p.base + here * p.pbytes, zo + p.own)
+                                             : Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes,
+                                                                             zf + p.colo[dff]);
+                        v = c * v + (R(1) - c) * x;
+                    }
+                }
+            }
         }
         return v;
     }
 }
 
-template <typename T, int FORM = FORM_S, int I = 0>
+// WALL: interpolated wall (p.bc set); else halfway bounce-back
+template <typename T, int FORM = FORM_S, bool WALL = false, int I = 0>
 __device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo,
                                        typename RealOf<T>::type (&g)[27])
 {
-    g[I] = pull_one<T, I, FORM>(p, zo, zmo, zpo);
-    if constexpr (I + 1 < 27) gather<T, FORM, I + 1>(p, zo, zmo, zpo, g);
+    g[I] = pull_one<T, I, FORM, WALL>(p, zo, zmo, zpo);
+    if constexpr (I + 1 < 27) gather<T, FORM, WALL, I + 1>(p, zo, zmo, zpo, g);
 }
 
 // two-buffer store: g*_i(x) into slot i of node x of the other buffer

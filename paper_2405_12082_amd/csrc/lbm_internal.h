@@ -21,6 +21,7 @@ struct Geom {
     const float *sigma;      // [n_sigma]: sin(2 pi n / T) for n < force_off_step
     long long n_sigma;
     const long long *step_dev;  // device step counter (graph-safe)
+    const double *bcoef;        // [9][P] interpolated-wall coefficients (see pull_one), null: bounce-back
     float omega, accel_z;
 };
 
@@ -69,7 +70,7 @@ hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf,
 hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
                                   int nsteps, unsigned *bar, int blocks, int per_group, int pipes_per_group,
                                   hipStream_t s);
-int persistent_blocks_per_cu(int storage, int aa, int block);
+int persistent_blocks_per_cu(int storage, int aa, int wall, int block);
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
 hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
                           int step_off, hipStream_t s);

@@ -97,12 +97,12 @@ __device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type 
 // One tile of one time step (column k of the tile, its z planes): gather of
 // g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
 // For the AA modes src and dst are the same buffer.
-template <typename T, int MODE>
+template <typename T, int MODE, bool WALL = false>
 __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *src, T *dst,
                                           long long n)
 {
     const int k = tc.k;
-    const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
+    const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
     const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const float sig = sigma_of(g, n);
@@ -115,7 +115,7 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
         const unsigned zo = (unsigned)z * rowb;
         const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
         typename RealOf<T>::type v[27];
-        gather<T, FORM>(p, zo, zmo, zpo, v);
+        gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         collide<T>(g, v, sig, px, py, pq, z);
         if constexpr (MODE == STEP_AB)
             store_all<T>(pout, p.pbytes, zo + p.own, v);
@@ -126,13 +126,13 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
     }
 }
 
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, bool WALL>
 __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
                                                                T *__restrict__ dst, int step_off)
 {
     const TileCoord tc = decode_tile(t, BLOCK);
     if (tc.k >= g.ncol) return;
-    step_tile<T, STEP_AB>(g, t, tc, src, dst, *g.step_dev + step_off);
+    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, *g.step_dev + step_off);
 }
 
 // AA pattern: one buffer, updated in place (no __restrict__: reads and
@@ -199,7 +199,7 @@ __device__ __forceinline__ bool group_barrier(unsigned *gb, unsigned *err, unsig
 // alternate: step j reads buf[(par + j) & 1].  AA pattern: one buffer
 // (buf0), par is the parity of the first step.
 constexpr int PERSIST_CHUNK = 2;
-template <typename T, int BLOCK, bool AA>
+template <typename T, int BLOCK, bool AA, bool WALL>
 __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const Tiles t, T *buf0, T *buf1, int par,
                                                            int nsteps, unsigned *bar, int per_group,
                                                            int pipes_per_group)
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const T
                     else
                         step_tile<T, STEP_AA_EVEN>(g, t, tc, buf0, buf0, n0 + j);
                 } else {
-                    step_tile<T, STEP_AB>(g, t, tc, src, dst, n0 + j);
+                    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, n0 + j);
                 }
             }
             if (threadIdx.x == 0) ticket = nxt;
@@ -295,7 +295,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* [BLOCK
             for (int q = 0; q < NV; ++q) v[q] += lds[w * NV + q];
 }
 
-template <typename T, int BLOCK, int FORM>
+template <typename T, int BLOCK, int FORM, bool WALL>
 __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, const T *__restrict__ state,
                                                     const ObserveArgs o, int step_off)
 {
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     double psum[4] = {0, 0, 0, 0};
     int cnt = 0;
     if (active) {
-        const Pull<T> p = make_pull(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
+        const Pull<T> p = make_pull(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
         const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
         const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
         const unsigned xy = g.colxy[k];
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
         using R = typename RealOf<T>::type;
         for (int z = z0; z < z1; ++z) {
             R v[27];
-            gather<T, FORM>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
+            gather<T, FORM, WALL>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
             R ax, ay, az;
             body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
             const Moments<R> m = moments_of<R>(v);
@@ -454,55 +454,83 @@ __global__ __launch_bounds__(256) void k_reduce_profile(const double *__restrict
 }
 
 // ---------------------------------------------------------------- state writers
-// Writers of a state g in a buffer form: FORM_S stores in slot j of node y
-// the value g_j(y + c_j) when y + c_j is fluid, else g_opp(j)(y) (inverse of
-// the bounce-back pull); FORM_W the same with slots j and opp(j) exchanged;
-// FORM_N stores g_j(y) in slot j.
-template <int FORM, int J>
-__device__ __forceinline__ void writer_source(const int (&col)[9], int k, int &src_col, int &src_dir, int &dz)
-{
-    if constexpr (FORM == FORM_N) {
-        src_col = k;
-        src_dir = J;
-        dz = 0;
-    } else {
-        constexpr int j = FORM == FORM_W ? OPP(J) : J;  // S-form slot stored in physical slot J
-        const int sc = col[NSLOT(CX(j), CY(j))];
-        if (sc >= 0) {
-            src_col = sc;
-            src_dir = j;
-            dz = CZ(j);
-        } else {
-            src_col = k;
-            src_dir = OPP(j);
-            dz = 0;
-        }
-    }
-}
-
+// Writers of a state g in a buffer form: FORM_N stores g_j(y) in slot j;
+// FORM_S stores in slot j of node y the value that the pull reads: g_j(y +
+// c_j) when y + c_j is fluid; else (a wall link of node y, population i =
+// opp(j)) the value F with pull(F) = g_i(y): F = g_i(y) for the bounce-back,
+// and for the interpolated wall F solves c F + (1 - c) X = g_i(y), where X is
+// g_i(y + c_i) (own-node mode, y + c_i fluid: slot i of y is pulled by y + c_i)
+// or g_j(y) (far mode: slot j of y + c_i is pulled back by y); when y + c_i is
+// solid too, F and slot i of y are the two wall values of y along this line
+// and solve a 2x2 system.  FORM_W: FORM_S with slots j and opp(j) exchanged.
+// Computed in FP64, stored in the buffer's type.
 __device__ __forceinline__ int wrap_z(int z, int dz, int nz) { return dz == 0 ? z : (dz > 0 ? wrap_p(z, nz) : wrap_m(z, nz)); }
 
-// initial state f = f^eq(1, (0, 0, u0(r))): g_j depends only on the column
-template <typename T, int FORM, int J = 0>
-__device__ __forceinline__ void init_slots(T *pipe, const Geom &g, const int (&col)[9], const float *u0, int k,
-                                           int z, const Axis<typename RealOf<T>::type> &zero)
+struct SrcDense {  // populations [27][nz][ny][nx] of one pipe (float)
+    const float *pops;
+    size_t plane, popstride;
+    const unsigned *colxy;
+    int nx;
+    template <int D> __device__ double get(int col, int z) const
+    {
+        const unsigned xy = colxy[col];
+        return (double)pops[D * popstride + (size_t)z * plane + (size_t)(xy >> 16) * nx + (xy & 0xffff)];
+    }
+};
+
+struct SrcEq {  // f^eq(1, (0, 0, u0(column))) - w
+    const float *u0;
+    template <int D> __device__ double get(int col, int) const
+    {
+        const Axis<double> zero = axis_factors(0.0);
+        return feq_dev<D, double>(0.0, zero, zero, axis_factors((double)u0[col]));
+    }
+};
+
+template <typename T, int FORM, typename Src, int J = 0>
+__device__ __forceinline__ void write_slots(T *pipe, const Geom &g, const int (&col)[9], const Src &src, int k, int z)
 {
-    using R = typename RealOf<T>::type;
-    R v;
+    double v;
     if constexpr (FORM == FORM_N) {
-        v = feq_dev<J, R>(R(0), zero, zero, axis_factors(R(u0[k])));
+        v = src.template get<J>(k, z);
     } else {
         constexpr int j = FORM == FORM_W ? OPP(J) : J;  // S-form slot stored in physical slot J
-        const int sc = col[NSLOT(CX(j), CY(j))];
-        if (sc >= 0)
-            v = feq_dev<j, R>(R(0), zero, zero, axis_factors(R(u0[sc])));
-        else
-            v = feq_dev<OPP(j), R>(R(0), zero, zero, axis_factors(R(u0[k])));
+        constexpr int d = NSLOT(CX(j), CY(j));
+        const int sc = col[d];
+        if (sc >= 0) {
+            v = src.template get<j>(sc, wrap_z(z, CZ(j), g.nz));
+        } else {
+            constexpr int i = OPP(j);
+            v = src.template get<i>(k, z);  // bounce-back
+            if constexpr (d != 4) {
+                if (g.bcoef) {
+                    const double cf = g.bcoef[d * g.P + k];
+                    if (cf != 1.0) {
+                        const double gj = src.template get<j>(k, z);
+                        if (cf < 0.0) {
+                            const double c = -cf;
+                            v = (v - (1.0 - c) * gj) / c;
+                        } else {
+                            const int sf = col[8 - d];
+                            if (sf >= 0) {
+                                v = (v - (1.0 - cf) * src.template get<i>(sf, wrap_z(z, CZ(i), g.nz))) / cf;
+                            } else {
+                                const double c2 = g.bcoef[(8 - d) * g.P + k];
+                                v = (c2 * v - (1.0 - cf) * gj) / (cf * c2 - (1.0 - cf) * (1.0 - c2));
+                            }
+                        }
+                    }
+                }
+            }
+        }
     }
-    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
-    if constexpr (J + 1 < 27) init_slots<T, FORM, J + 1>(pipe, g, col, u0, k, z, zero);
+    using R = typename RealOf<T>::type;
+    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T),
+                             (R)v);
+    if constexpr (J + 1 < 27) write_slots<T, FORM, Src, J + 1>(pipe, g, col, src, k, z);
 }
 
+// initial state f = f^eq(1, (0, 0, u0(r))) (u0 = 0: rest)
 template <typename T, int FORM>
 __global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restrict__ u0, T *__restrict__ state)
 {
@@ -514,22 +542,7 @@ __global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restr
     const int z = (int)(r % g.nz), b = (int)(r / g.nz);
     int col[9];
     load_columns(g, k, col);
-    using R = typename RealOf<T>::type;
-    const Axis<R> zero = axis_factors(R(0));
-    init_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, u0, k, z, zero);
-}
-
-template <typename T, int FORM, int J = 0>
-__device__ __forceinline__ void set_slots(T *pipe, const Geom &g, const int (&col)[9], const float *src, int k, int z,
-                                          size_t plane, size_t popstride)
-{
-    int sc, dir, dz;
-    writer_source<FORM, J>(col, k, sc, dir, dz);
-    const unsigned xy = g.colxy[sc];
-    const int zs = wrap_z(z, dz, g.nz);
-    const float v = src[dir * popstride + (size_t)zs * plane + (size_t)(xy >> 16) * g.nx + (xy & 0xffff)];
-    Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T), v);
-    if constexpr (J + 1 < 27) set_slots<T, FORM, J + 1>(pipe, g, col, src, k, z, plane, popstride);
+    write_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, SrcEq{u0}, k, z);
 }
 
 template <typename T, int FORM>
@@ -544,7 +557,8 @@ __global__ __launch_bounds__(256) void k_set_pops(const Geom g, const float *__r
     int col[9];
     load_columns(g, k, col);
     const size_t plane = (size_t)g.nx * g.ny, popstride = (size_t)g.nz * plane;
-    set_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, pops + (size_t)b * 27 * popstride, k, z, plane, popstride);
+    const SrcDense src{pops + (size_t)b * 27 * popstride, plane, popstride, g.colxy, g.nx};
+    write_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, src, k, z);
 }
 
 __global__ void k_fill(uint32_t *p, size_t n)
@@ -564,16 +578,25 @@ __global__ void k_set_step(long long *p, long long v, int add)
 // ---------------------------------------------------------------- launchers
 static int grid_of(const Tiles &t) { return (int)(t.count() * t.nb); }
 
-template <typename T>
-static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
+template <typename T, bool WALL>
+static hipError_t step_wall(const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
 {
     const dim3 grid(grid_of(t));
     switch (t.block) {
-    case 64: hipLaunchKernelGGL((k_step<T, 64>), grid, dim3(64), 0, s, g, t, (const T *)src, (T *)dst, off); break;
-    case 128: hipLaunchKernelGGL((k_step<T, 128>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off); break;
-    default: hipLaunchKernelGGL((k_step<T, 256>), grid, dim3(256), 0, s, g, t, (const T *)src, (T *)dst, off); break;
+    case 64: hipLaunchKernelGGL((k_step<T, 64, WALL>), grid, dim3(64), 0, s, g, t, (const T *)src, (T *)dst, off); break;
+    case 128:
+        hipLaunchKernelGGL((k_step<T, 128, WALL>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off);
+        break;
+    default:
+        hipLaunchKernelGGL((k_step<T, 256, WALL>), grid, dim3(256), 0, s, g, t, (const T *)src, (T *)dst, off);
+        break;
     }
     return hipGetLastError();
+}
+template <typename T>
+static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
+{
+    return g.bcoef ? step_wall<T, true>(g, t, src, dst, off, s) : step_wall<T, false>(g, t, src, dst, off, s);
 }
 
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
@@ -615,7 +638,7 @@ hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf,
     return storage == 1 ? step_aa_mode<__half>(g, t, buf, odd, off, s) : step_aa_mode<float>(g, t, buf, odd, off, s);
 }
 
-template <typename T, int BLOCK, bool AA>
+template <typename T, int BLOCK, bool AA, bool WALL>
 static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
                                int blocks, int per_group, int ppg, hipStream_t s)
 {
@@ -623,26 +646,29 @@ static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1
     Tiles tt = t;
     T *p0 = (T *)b0, *p1 = (T *)b1;
     void *args[] = {&gg, &tt, &p0, &p1, &par, &nsteps, &bar, &per_group, &ppg};
-    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK, AA>;
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) =
+        &k_step_persistent<T, BLOCK, AA, WALL>;
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
 }
 
-template <typename T, bool AA>
+template <typename T, bool AA, bool WALL>
 static hipError_t persistent_block(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
                                    int blocks, int per_group, int ppg, hipStream_t s)
 {
     switch (t.block) {
-    case 64: return persistent_t<T, 64, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    case 128: return persistent_t<T, 128, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    default: return persistent_t<T, 256, AA>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 64: return persistent_t<T, 64, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 128: return persistent_t<T, 128, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    default: return persistent_t<T, 256, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
     }
 }
+// kinds: two buffers + bounce-back, AA + bounce-back, two buffers + interpolated wall
 template <typename T>
 static hipError_t persistent_pattern(int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
                                      unsigned *bar, int blocks, int per_group, int ppg, hipStream_t s)
 {
-    return aa ? persistent_block<T, true>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s)
-              : persistent_block<T, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    if (aa) return persistent_block<T, true, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    if (g.bcoef) return persistent_block<T, false, true>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    return persistent_block<T, false, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
 }
 
 hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
@@ -656,26 +682,29 @@ hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tile
     return persistent_pattern<float>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
 }
 
-template <typename T, int BLOCK, bool AA> static int occ_t()
+template <typename T, int BLOCK, bool AA, bool WALL> static int occ_t()
 {
     int n = 0;
-    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) = &k_step_persistent<T, BLOCK, AA>;
+    void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) =
+        &k_step_persistent<T, BLOCK, AA, WALL>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(fn), BLOCK, 0) != hipSuccess)
         return 0;
     return n;
 }
-template <typename T, bool AA> static int occ_block(int block)
+template <typename T, bool AA, bool WALL> static int occ_block(int block)
 {
-    return block == 64 ? occ_t<T, 64, AA>() : (block == 128 ? occ_t<T, 128, AA>() : occ_t<T, 256, AA>());
+    return block == 64 ? occ_t<T, 64, AA, WALL>()
+                       : (block == 128 ? occ_t<T, 128, AA, WALL>() : occ_t<T, 256, AA, WALL>());
 }
-template <typename T> static int occ_pattern(int aa, int block)
+template <typename T> static int occ_pattern(int aa, int wall, int block)
 {
-    return aa ? occ_block<T, true>(block) : occ_block<T, false>(block);
+    if (aa) return occ_block<T, true, false>(block);
+    return wall ? occ_block<T, false, true>(block) : occ_block<T, false, false>(block);
 }
-int persistent_blocks_per_cu(int storage, int aa, int block)
+int persistent_blocks_per_cu(int storage, int aa, int wall, int block)
 {
-    return storage == 2 ? occ_pattern<double>(aa, block)
-                        : (storage == 1 ? occ_pattern<__half>(aa, block) : occ_pattern<float>(aa, block));
+    return storage == 2 ? occ_pattern<double>(aa, wall, block)
+                        : (storage == 1 ? occ_pattern<__half>(aa, wall, block) : occ_pattern<float>(aa, wall, block));
 }
 
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
@@ -684,10 +713,11 @@ hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *s
     return storage == 1 ? step_t<__half>(g, t, src, dst, off, s) : step_t<float>(g, t, src, dst, off, s);
 }
 
-template <typename T, int FORM>
+template <typename T, int FORM, bool WALL = false>
 static void observe_t(const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_observe<T, 256, FORM>), dim3(grid_of(t)), dim3(256), 0, s, g, t, (const T *)state, o, off);
+    hipLaunchKernelGGL((k_observe<T, 256, FORM, WALL>), dim3(grid_of(t)), dim3(256), 0, s, g, t, (const T *)state, o,
+                       off);
 }
 template <typename T>
 static void observe_form(int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o, int off,
@@ -697,6 +727,8 @@ static void observe_form(int form, const Geom &g, const Tiles &t, const void *st
         observe_t<T, FORM_N>(g, t, state, o, off, s);
     else if (form == FORM_W)
         observe_t<T, FORM_W>(g, t, state, o, off, s);
+    else if (g.bcoef)
+        observe_t<T, FORM_S, true>(g, t, state, o, off, s);
     else
         observe_t<T, FORM_S>(g, t, state, o, off, s);
 }

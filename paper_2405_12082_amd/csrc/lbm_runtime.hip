@@ -40,7 +40,7 @@ struct Layout {
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
     // workspace offsets
-    size_t off_state[2], off_nbr, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
+    size_t off_state[2], off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
     size_t total = 0;
@@ -80,7 +80,10 @@ int build_layout(const lbm_config *cfg, Layout &L)
     }
     if (c.storage < 0 || c.storage > 2) return bad("storage must be 0 (FP32), 1 (FP16) or 2 (FP64)");
     if (c.storage == 2 && c.adjoint == 1) return bad("the adjoint of the FP64 forward is FP64 (adjoint = 2)");
-    if (c.wall != 0) return bad("wall must be 0 (halfway bounce-back)");
+    if (c.wall != 0 && c.wall != 1) return bad("wall must be 0 (halfway bounce-back) or 1 (interpolated, Bouzidi)");
+    if (c.wall == 1 && !(c.radius > 0.0)) return bad("the interpolated wall needs a pipe wall (radius > 0)");
+    if (c.wall == 1 && c.pattern != 0) return bad("the interpolated wall needs the two-buffer pattern (pattern = 0)");
+    if (c.wall == 1 && c.adjoint != 0) return bad("the adjoint supports the bounce-back wall only (wall = 0)");
     if (c.pattern != 0 && c.pattern != 1) return bad("pattern must be 0 (two buffers) or 1 (AA, in place)");
     if (c.pattern == 1 && c.adjoint != 0) return bad("the adjoint needs the two-buffer pattern (pattern = 0)");
     if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");
@@ -129,6 +132,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_state[0] = take(L.state_bytes);
     L.off_state[1] = c.pattern == 1 ? L.off_state[0] : take(L.state_bytes);  // AA: one buffer
     L.off_nbr = take(9 * P * sizeof(int));
+    L.off_bcoef = c.wall == 1 ? take(9 * P * sizeof(double)) : 0;
     L.off_colxy = take(P * sizeof(unsigned));
     L.off_fshape = take(B * 3 * P * sizeof(float));
     L.off_ztab = take(2 * (size_t)c.nz * sizeof(float));
@@ -177,6 +181,21 @@ void mode_shape(const lbm_config &c, double amp, int m, double phi, int x, int y
     out[0] = Fr * std::cos(th) - Ft * std::sin(th);
     out[1] = Fr * std::sin(th) + Ft * std::cos(th);
     out[2] = Fz;
+}
+
+// Interpolated wall, Eqs. (fbc1)/(fbc2): for fluid column (x, y) whose
+// in-plane neighbour at offset (dx, dy) is solid, Delta in (0, 1] is the
+// fraction of that link at which it crosses r = R (ray-circle
+// intersection; c_z does not change r).  Coefficient of the pull (see
+// pull_one): +1/(2 Delta) for Delta >= 1/2, -2 Delta for Delta < 1/2 when the
+// node on the other side, (x - dx, y - dy), is fluid, else +1 (bounce-back).
+double wall_coefficient(const lbm_config &c, int x, int y, int dx, int dy, bool far_fluid)
+{
+    const double px = x - 0.5 * (c.nx - 1), py = y - 0.5 * (c.ny - 1);
+    const double a = dx * dx + dy * dy, b = 2.0 * (px * dx + py * dy), q = px * px + py * py - c.radius * c.radius;
+    const double delta = (-b + std::sqrt(b * b - 4.0 * a * q)) / (2.0 * a);
+    if (delta >= 0.5) return 1.0 / (2.0 * delta);
+    return far_fluid ? -2.0 * delta : 1.0;
 }
 
 double loglaw(const lbm_config &c, double r)
@@ -340,6 +359,15 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
                 nbr[(size_t)((dy + 1) * 3 + (dx + 1)) * P + k] = L.colmap[(size_t)y * g.nx + x];
             }
     }
+    std::vector<double> bcoef(g.wall == 1 ? 9 * P : 0, 0.0);
+    if (g.wall == 1)
+        for (int k = 0; k < L.ncol; ++k)
+            for (int d = 0; d < 9; ++d)
+                if (nbr[(size_t)d * P + k] < 0) {
+                    const int dx = d % 3 - 1, dy = d / 3 - 1;
+                    const bool far_fluid = nbr[(size_t)(8 - d) * P + k] >= 0;
+                    bcoef[(size_t)d * P + k] = wall_coefficient(g, L.colx[k], L.coly[k], dx, dy, far_fluid);
+                }
     // trigger-force shape sums per pipe and per column, Eq. (TurbForce)
     std::vector<float> fshape(B * 3 * P, 0.f);
     std::vector<double> modes((size_t)2 * kMaxModes * 3 * P, 0.0);
@@ -382,6 +410,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = h2d(L.off_nbr, nbr.data(), nbr.size() * sizeof(int));
     if (e == hipSuccess) e = h2d(L.off_colxy, colxy.data(), colxy.size() * sizeof(unsigned));
+    if (e == hipSuccess && g.wall == 1) e = h2d(L.off_bcoef, bcoef.data(), bcoef.size() * sizeof(double));
     if (e == hipSuccess) e = h2d(L.off_fshape, fshape.data(), fshape.size() * sizeof(float));
     if (e == hipSuccess) e = h2d(L.off_ztab, ztab.data(), ztab.size() * sizeof(float));
     if (e == hipSuccess) e = h2d(L.off_sigma, sig.data(), sig.size() * sizeof(float));
@@ -403,6 +432,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     G.pstride = g.nz * L.P;
     G.pipe = 27LL * g.nz * L.P;
     G.nbr = (const int *)(ws + L.off_nbr);
+    G.bcoef = g.wall == 1 ? (const double *)(ws + L.off_bcoef) : nullptr;
     G.colxy = (const unsigned *)(ws + L.off_colxy);
     G.fshape = (const float *)(ws + L.off_fshape);
     G.ztab = (const float *)(ws + L.off_ztab);
@@ -481,7 +511,7 @@ int lbm_step_persistent(lbm_ctx *c, int32_t n)
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int aa = c->cfg.pattern == 1;
-    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, aa, c->L.step.block);
+    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, aa, c->cfg.wall, c->L.step.block);
     if (per_cu < 1 || cus < 1) return fail(c, LBM_EHIP, "lbm_step_persistent: occupancy query failed");
     Tiles t = c->L.step;
     t.b0 = 0;

@@ -52,7 +52,8 @@ def test_fp16_storage_halves_the_state():
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(batch=0), dict(tau=0.5), dict(tau=0.4), dict(n_modes=7), dict(n_modes=-1),
-    dict(storage=3), dict(storage=2, adjoint=1), dict(adjoint=3), dict(wall=1), dict(pattern=2),
+    dict(storage=3), dict(storage=2, adjoint=1), dict(adjoint=3), dict(wall=2), dict(wall=1, pattern=1),
+    dict(wall=1, adjoint=1), dict(wall=1, radius=0.0), dict(pattern=2),
     dict(pattern=1, adjoint=1),
     dict(init=2), dict(radius=12.0),
     dict(block=96), dict(zchunk=65), dict(n_modes=2, period=0.0), dict(radius=0.4),
@@ -94,6 +95,15 @@ def test_aa_pattern_keeps_one_state_buffer():
     aa = P.describe(P.make_config(**cfg))
     assert aa.state_bytes == ab.state_bytes and aa.bytes_per_update == ab.bytes_per_update
     assert ab.workspace_bytes - aa.workspace_bytes == ab.state_bytes
+
+
+def test_interpolated_wall_is_a_valid_configuration():
+    cfg = LI.preset("laminar")
+    a = P.describe(P.make_config(**cfg))
+    cfg["wall"] = 1
+    b = P.describe(P.make_config(**cfg))
+    assert b.n_fluid_nodes == a.n_fluid_nodes
+    assert b.workspace_bytes - a.workspace_bytes >= 9 * b.plane_pitch * 8  # coefficient table
 
 
 def test_periodic_box_layout():
