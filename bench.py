@@ -73,7 +73,7 @@ def _events(stream):
     return a, b
 
 
-def leg_fp16(steps=500, storage=1, pattern=0):
+def leg_fp16(steps=500, storage=1, pattern=0, wall=0):
     """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
     import torch
     import lbm_inputs as LI
@@ -81,6 +81,7 @@ def leg_fp16(steps=500, storage=1, pattern=0):
     cfg = LI.preset("turbulent")
     cfg["storage"] = storage
     cfg["pattern"] = pattern
+    cfg["wall"] = wall
     amps = LI.preset_amplitudes(cfg)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -108,6 +109,14 @@ def leg_aa(steps=500):
     place (half the state memory; same results as two buffers)."""
     r = leg_fp16(steps, storage=0, pattern=1)
     r["pattern"] = "AA (in place)"
+    return r
+
+
+def leg_bouzidi(steps=500):
+    """The turbulent pipe in FP32 with the interpolated wall of Eqs.
+    (fbc1)/(fbc2) instead of the halfway bounce-back."""
+    r = leg_fp16(steps, storage=0, pattern=0, wall=1)
+    r["wall"] = "interpolated (Bouzidi)"
     return r
 
 
@@ -297,7 +306,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,aa,batched,adjoint,precision",
+    ap.add_argument("--legs", default="fp16,aa,bouzidi,batched,adjoint,precision",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -426,7 +435,8 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     for leg in legs:
-        extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "batched": leg_batched, "adjoint": leg_adjoint,
+        extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "batched": leg_batched,
+                      "adjoint": leg_adjoint,
                       "precision": leg_precision}[leg]()
     if extra:
         out["extra"] = extra

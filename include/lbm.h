@@ -78,7 +78,7 @@ typedef struct {
     int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1));
                              1: interpolated wall of Eqs. (fbc1)/(fbc2) with the exact
                              fraction Delta of each cut link at r = R (two-buffer
-                             pattern, no adjoint) */
+                             pattern) */
     int32_t pattern;      /* 0: two buffers (A/B); 1: AA, one buffer updated in place (even
                              steps read and write a node's own slots, odd steps its
                              neighbours'); same results, half the state memory; no

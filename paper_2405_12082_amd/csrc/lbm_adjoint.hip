@@ -19,21 +19,43 @@ namespace lbm {
 // vector-Jacobian arithmetic (float or double); the forward state is decoded
 // to float as in the forward kernel, then promoted to R.
 
-// mu_j(y) = lambda_j(y + c_j) if y + c_j is fluid, else lambda_opp(j)(y):
-// the transpose of the pull gather with halfway bounce-back.
-template <typename R, int J = 0>
+// mu = S^T lambda, the transpose of the pull.  Bounce-back wall: mu_j(y) =
+// lambda_j(y + c_j) if y + c_j is fluid, else lambda_opp(j)(y).  The
+// interpolated wall (coefficients cf as in the forward pull) adds, for the
+// post-collision value g*_j(y):
+//  - y + c_j solid: it enters the wall link (y, opp(j)) with weight c = |cf|;
+//  - y - c_j solid, link (y, j) in own-node mode (cf > 0): weight 1 - cf in
+//    that link (X = g*_j(y));
+//  - y + c_j fluid with y + 2 c_j solid, link (y + c_j, opp(j)) in far mode
+//    (cf < 0): weight 1 + cf in that link (X = g*_j of the node behind it).
+// Coefficient tables hold 0 for fluid slots, so the mode tests need no
+// neighbour masks.
+template <typename R, bool WALL, int J = 0>
 __device__ __forceinline__ void gather_transpose(const R *__restrict__ lam, int pstride, int P, const int (&col)[9],
-                                                 int k, int z, int zm, int zp, R (&mu)[27])
+                                                 int k, int z, int zm, int zp, const double *bcoef, R (&mu)[27])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
     constexpr int d = NSLOT(cx, cy);
     const int zs = cz == 0 ? z : (cz > 0 ? zp : zm);
     const int sc = col[d];
-    if (d == 4 || sc >= 0)
+    if (d == 4 || sc >= 0) {
         mu[J] = lam[(size_t)J * pstride + (size_t)zs * P + sc];
-    else
+        if constexpr (WALL && d != 4) {
+            const double cf = bcoef[(size_t)d * P + sc];
+            if (cf < 0.0) mu[J] += R(1.0 + cf) * lam[(size_t)OPP(J) * pstride + (size_t)zs * P + sc];
+        }
+    } else {
         mu[J] = lam[(size_t)OPP(J) * pstride + (size_t)z * P + k];
-    if constexpr (J + 1 < 27) gather_transpose<R, J + 1>(lam, pstride, P, col, k, z, zm, zp, mu);
+        if constexpr (WALL) {
+            const double cf = bcoef[(size_t)d * P + k];
+            mu[J] *= R(cf > 0.0 ? cf : -cf);
+        }
+    }
+    if constexpr (WALL && d != 4) {
+        const double cf = bcoef[(size_t)(8 - d) * P + k];
+        if (cf > 0.0 && cf != 1.0) mu[J] += R(1.0 - cf) * lam[(size_t)J * pstride + (size_t)z * P + k];
+    }
+    if constexpr (J + 1 < 27) gather_transpose<R, WALL, J + 1>(lam, pstride, P, col, k, z, zm, zp, bcoef, mu);
 }
 
 // per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
@@ -124,7 +146,7 @@ __device__ __forceinline__ void write_lambda(R *__restrict__ lam, int pstride, s
 #define LBM_ADJ_OCCUPANCY
 #endif
 
-template <typename T, typename R, int BLOCK>
+template <typename T, typename R, int BLOCK, bool WALL>
 __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
@@ -149,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
         using W = typename RealOf<T>::type;
         W v[27];
-        gather<T>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
+        gather<T, FORM_S, WALL>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
         const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
         // the forward step's body acceleration (computed in its arithmetic type W), then promoted
         W fax, fay, faz;
@@ -178,7 +200,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
         R mu[27];
         if (a.has_next) {
-            gather_transpose<R>(lin, g.pstride, g.P, col, k, z, zm, zp, mu);
+            gather_transpose<R, WALL>(lin, g.pstride, g.P, col, k, z, zm, zp, g.bcoef, mu);
         } else {
 #pragma unroll
             for (int i = 0; i < 27; ++i) mu[i] = R(0);
@@ -265,23 +287,25 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ cols
     if (threadIdx.x == 0) grad[(size_t)b * nq + q] += sigma * lds[0];
 }
 
+template <typename T, typename R>
+static void adjoint_wall(const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)(t.count() * t.nb));
+    if (g.bcoef)
+        hipLaunchKernelGGL((k_adjoint<T, R, 256, true>), grid, dim3(256), 0, s, g, t, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<T, R, 256, false>), grid, dim3(256), 0, s, g, t, a);
+}
+
 hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
                           hipStream_t s)
 {
-    const dim3 grid((unsigned)(t.count() * t.nb));
-    if (storage == 2) {  // FP64 forward: FP64 adjoint
-        hipLaunchKernelGGL((k_adjoint<double, double, 256>), grid, dim3(256), 0, s, g, t, a);
-    } else if (precision == 2) {
-        if (storage == 1)
-            hipLaunchKernelGGL((k_adjoint<__half, double, 256>), grid, dim3(256), 0, s, g, t, a);
-        else
-            hipLaunchKernelGGL((k_adjoint<float, double, 256>), grid, dim3(256), 0, s, g, t, a);
-    } else {
-        if (storage == 1)
-            hipLaunchKernelGGL((k_adjoint<__half, float, 256>), grid, dim3(256), 0, s, g, t, a);
-        else
-            hipLaunchKernelGGL((k_adjoint<float, float, 256>), grid, dim3(256), 0, s, g, t, a);
-    }
+    if (storage == 2)  // FP64 forward: FP64 adjoint
+        adjoint_wall<double, double>(g, t, a, s);
+    else if (precision == 2)
+        storage == 1 ? adjoint_wall<__half, double>(g, t, a, s) : adjoint_wall<float, double>(g, t, a, s);
+    else
+        storage == 1 ? adjoint_wall<__half, float>(g, t, a, s) : adjoint_wall<float, float>(g, t, a, s);
     return hipGetLastError();
 }
 

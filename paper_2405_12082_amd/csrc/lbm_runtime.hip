@@ -83,7 +83,6 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.wall != 0 && c.wall != 1) return bad("wall must be 0 (halfway bounce-back) or 1 (interpolated, Bouzidi)");
     if (c.wall == 1 && !(c.radius > 0.0)) return bad("the interpolated wall needs a pipe wall (radius > 0)");
     if (c.wall == 1 && c.pattern != 0) return bad("the interpolated wall needs the two-buffer pattern (pattern = 0)");
-    if (c.wall == 1 && c.adjoint != 0) return bad("the adjoint supports the bounce-back wall only (wall = 0)");
     if (c.pattern != 0 && c.pattern != 1) return bad("pattern must be 0 (two buffers) or 1 (AA, in place)");
     if (c.pattern == 1 && c.adjoint != 0) return bad("the adjoint needs the two-buffer pattern (pattern = 0)");
     if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");

@@ -37,27 +37,32 @@ TINY = dict(nx=12, ny=12, nz=8, batch=1, radius=5.0, tau=0.6, accel_z=1e-5, n_mo
 TINY_AMPS = np.array([1e-4, 2e-4, 3e-4, 1.5e-4])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod, precision):
+@pytest.mark.parametrize("precision,wall", [("fp32", 0), ("fp64", 0), ("fp32", 1), ("fp64", 1)])
+def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod, precision, wall):
+    """wall = 1: the interpolated wall; the 12x12 section (R = 5) has cut
+    links in both modes of the interpolation and nodes with two cut links on
+    one line."""
     O = oracle_mod
-    run = gpu.EnergyAdjoint(TINY, 20, 40, checkpoint_every=7, precision=precision)
+    cfg = dict(TINY, wall=wall)
+    run = gpu.EnergyAdjoint(cfg, 20, 40, checkpoint_every=7, precision=precision)
     J, g = run.gradient(TINY_AMPS[None])
-    Jo, go = O.adjoint_gradient(O.make_config(**TINY), TINY_AMPS, 20, 40)
+    Jo, go = O.adjoint_gradient(O.make_config(**cfg), TINY_AMPS, 20, 40)
     err = np.abs(g[0] - go).max() / np.abs(go).max()
     _log(f"J gpu {J[0]:.10e} oracle {Jo:.10e}; gradient error vs oracle adjoint {err:.3e}")
     assert abs(J[0] - Jo) < 1e-5 * abs(Jo)  # FP32 state: u_z to ~1e-6 relative
     assert err < 1e-4
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-5), ("fp32", 1e-4)])
-def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol):
+@pytest.mark.parametrize("precision,tol,wall", [("fp64", 1e-5, 0), ("fp32", 1e-4, 0), ("fp64", 1e-5, 1)])
+def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol, wall):
     """2000 steps of a 16x16x32 pipe (R = 7) with the adjoint workload's
     physics: the GPU adjoint (FP32 forward) against the oracle's complex-step
-    tangent of the whole FP64 run (the exact derivative)."""
+    tangent of the whole FP64 run (the exact derivative); wall = 1 with the
+    interpolated wall."""
     O = oracle_mod
     cfg = LI.preset("adjoint")
     cfg.update(nx=16, ny=16, nz=32, radius=7.0, accel_z=2 * cfg["u_tau"] ** 2 / 7.0,
-               period=float(round(0.052 * 7.0 / cfg["u_tau"])), force_off_step=2000)
+               period=float(round(0.052 * 7.0 / cfg["u_tau"])), force_off_step=2000, wall=wall)
     amps = LI.preset_amplitudes(cfg)
     J, g = gpu.EnergyAdjoint(cfg, 1501, 2001, checkpoint_every=100, precision=precision).gradient(amps)
     Jt, gt = O.tangent_gradient(O.make_config(**cfg), amps[0], 1501, 2001)

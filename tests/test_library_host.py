@@ -53,7 +53,7 @@ def test_fp16_storage_halves_the_state():
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(batch=0), dict(tau=0.5), dict(tau=0.4), dict(n_modes=7), dict(n_modes=-1),
     dict(storage=3), dict(storage=2, adjoint=1), dict(adjoint=3), dict(wall=2), dict(wall=1, pattern=1),
-    dict(wall=1, adjoint=1), dict(wall=1, radius=0.0), dict(pattern=2),
+    dict(wall=1, radius=0.0), dict(pattern=2),
     dict(pattern=1, adjoint=1),
     dict(init=2), dict(radius=12.0),
     dict(block=96), dict(zchunk=65), dict(n_modes=2, period=0.0), dict(radius=0.4),
