@@ -156,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     int col[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
-    const Pull<T> p = make_pull((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
+    const Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const float *fs = g.fshape + (size_t)b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];

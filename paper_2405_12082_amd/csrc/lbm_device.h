@@ -112,27 +112,25 @@ template <> struct Codec<__half> {
 // Per-thread view of one pipe's population buffer for one column k:
 // byte offsets of the 9 in-plane neighbour columns (own column where the
 // neighbour is solid), a bit mask of the solid ones, and (interpolated wall
-// only) the column's wall coefficients.
-template <typename T> struct Pull {
+// only) where the column's wall coefficients are.
+template <typename T, bool WALL = false> struct Pull {
     const char *base;   // pipe base
     size_t pbytes;      // bytes between populations (nz * P * sizeof(T))
     unsigned colo[9];   // byte offset of the column in slot d within a plane
     unsigned wall;      // bit d set: slot d is solid
     unsigned own;       // byte offset of column k within a plane
-    const double *bc;   // interpolated wall: coefficient of slot d at bc[d * P]; null: bounce-back
+    const double *bc;   // interpolated wall: coefficient of slot d at bc[d * P] (0 for fluid slots)
     int P;
 };
 
-template <typename T>
-__device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k,
-                                             const double *bcoef = nullptr)
+template <typename T, bool WALL = false>
+__device__ __forceinline__ Pull<T, WALL> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k,
+                                                   const double *bcoef = nullptr)
 {
-    Pull<T> p;
+    Pull<T, WALL> p;
     p.base = reinterpret_cast<const char *>(pipe);
     p.pbytes = pstride * sizeof(T);
     p.own = (unsigned)k * sizeof(T);
-    p.bc = bcoef ? bcoef + k : nullptr;
-    p.P = P;
     p.wall = 0;
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
@@ -140,20 +138,18 @@ __device__ __forceinline__ Pull<T> make_pull(const T *pipe, size_t pstride, cons
         p.colo[d] = (unsigned)(c >= 0 ? c : k) * sizeof(T);
         if (c < 0) p.wall |= 1u << d;
     }
+    p.bc = WALL ? bcoef + k : nullptr;
+    p.P = P;
     return p;
 }
 
 // Pull streaming, Eq. (streaming): g_i(x, n) = g*_i(x - c_i, n-1) if x - c_i
-// is fluid.  Else the wall: halfway bounce-back g*_opp(i)(x, n-1) (the
-// Delta = 1/2 case of Eq. (fbc1)), or, with the interpolated wall of Eqs.
-// (fbc1)/(fbc2), c g*_opp(i)(x) + (1 - c) X with the column's coefficient
-// cf = +-c for the link: cf > 0 (Delta >= 1/2, c = 1/(2 Delta)): X =
-// g*_i(x); cf < 0 (Delta < 1/2 and x + c_i fluid, c = 2 Delta): X =
-// g*_opp(i)(x + c_i); cf = 1: bounce-back.  (Deviations g = f - w combine
-// like f: the weights sum to 1 and w_i = w_opp(i).)  zo/zmo/zpo: byte
-// offsets of planes z, z-1, z+1 (periodic in z).  FORM_N reads the own slot.
+// is fluid, else the halfway bounce-back g*_opp(i)(x, n-1) (the Delta = 1/2
+// case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
+// (periodic in z).  FORM_N reads the own slot.
 template <typename T, int I, int FORM, bool WALL>
-__device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo)
+__device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T, WALL> &p, unsigned zo, unsigned zmo,
+                                                             unsigned zpo)
 {
     if constexpr (FORM == FORM_N) {
         return Codec<T>::template ld<I>(p.base + I * p.pbytes, zo + p.own);
@@ -162,36 +158,81 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T> &p, u
         constexpr int d = NSLOT(-cx, -cy);
         constexpr int here = FORM == FORM_W ? OPP(I) : I;  // physical slot of g*_I
         const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
-        using R = typename RealOf<T>::type;
-        R v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
+        typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
         if constexpr (d != 4) {
-            if (p.wall & (1u << d)) {
-                v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
-                if constexpr (WALL) {
-                    const double cf = p.bc[d * p.P];
-                    if (cf != 1.0) {
-                        const R c = R(cf > 0.0 ? cf : -cf);
-                        constexpr int dff = 8 - d;  // slot of x + c_i
-                        const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
-                        const R x = cf > 0.0 ? Codec<T>::template ld<I>(p.base + here * p.pbytes, zo + p.own)
-                                             : Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes,
-                                                                             zf + p.colo[dff]);
-                        v = c * v + (R(1) - c) * x;
-                    }
-                }
-            }
+            if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
         }
         return v;
     }
 }
 
-// WALL: interpolated wall (p.bc set); else halfway bounce-back
+// Interpolated wall, Eqs. (fbc1)/(fbc2): a wall link's value becomes
+// c g*_opp(i)(x) + (1 - c) X (g*_opp(i)(x) is what the pull above read),
+// with the column's coefficient cf = +-c: cf > 0 (Delta >= 1/2, c =
+// 1/(2 Delta)): X = g*_i(x); cf < 0 (Delta < 1/2 and x + c_i fluid, c =
+// 2 Delta): X = g*_opp(i)(x + c_i); cf = 1: bounce-back (also stored for
+// fluid slots, where it leaves the value unchanged).  Deviations g = f - w
+// combine like f: the weights sum to 1 and w_i = w_opp(i).  The X loads of
+// a node are issued in groups (slots of the same shell share the FP16
+// scale), then combined, so a wave with wall columns waits once per group.
+template <typename T, int FORM, int ZC, int I = 0>
+__device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typename RealOf<T>::type (&cf)[9],
+                                           unsigned zo, unsigned zmo, unsigned zpo, typename RealOf<T>::type (&x)[27])
+{
+    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
+    constexpr int d = NSLOT(-cx, -cy);
+    if constexpr (d != 4 && cz == ZC) {
+        constexpr int here = FORM == FORM_W ? OPP(I) : I;
+        const bool own_mode = cf[d] > 0;
+        const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
+        const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
+        x[I] = own_mode ? Codec<T>::template ld<I>(p.base + here * p.pbytes, off)
+                        : Codec<T>::template ld<I>(p.base + OPP(here) * p.pbytes, off);
+    }
+    if constexpr (I + 1 < 27) wall_loads<T, FORM, ZC, I + 1>(p, cf, zo, zmo, zpo, x);
+}
+
+template <typename T, int ZC, int I = 0>
+__device__ __forceinline__ void wall_combine(const typename RealOf<T>::type (&cf)[9],
+                                             const typename RealOf<T>::type (&x)[27], typename RealOf<T>::type (&v)[27])
+{
+    using R = typename RealOf<T>::type;
+    constexpr int d = NSLOT(-CX(I), -CY(I));
+    if constexpr (d != 4 && CZ(I) == ZC) {
+        const R c = cf[d] > R(0) ? cf[d] : -cf[d];
+        v[I] = c * v[I] + (R(1) - c) * x[I];
+    }
+    if constexpr (I + 1 < 27) wall_combine<T, ZC, I + 1>(cf, x, v);
+}
+
+// WALL: interpolated wall (coefficients at p.bc); else halfway bounce-back
 template <typename T, int FORM = FORM_S, bool WALL = false, int I = 0>
-__device__ __forceinline__ void gather(const Pull<T> &p, unsigned zo, unsigned zmo, unsigned zpo,
+__device__ __forceinline__ void gather(const Pull<T, WALL> &p, unsigned zo, unsigned zmo, unsigned zpo,
                                        typename RealOf<T>::type (&g)[27])
 {
     g[I] = pull_one<T, I, FORM, WALL>(p, zo, zmo, zpo);
-    if constexpr (I + 1 < 27) gather<T, FORM, WALL, I + 1>(p, zo, zmo, zpo, g);
+    if constexpr (I + 1 < 27) {
+        gather<T, FORM, WALL, I + 1>(p, zo, zmo, zpo, g);
+    } else if constexpr (WALL) {
+        if (p.wall & 0x1efu) {  // a solid in-plane neighbour (slot 4 is the column itself)
+            // coefficients (1 for fluid slots: the value stays), then the X
+            // values in three groups of eight (c_z = -1, 0, +1)
+            using R = typename RealOf<T>::type;
+            R cf[9];
+#pragma unroll
+            for (int d = 0; d < 9; ++d) {
+                const double c = p.bc[d * p.P];
+                cf[d] = (p.wall & (1u << d)) ? R(c) : R(1);
+            }
+            R x[27];
+            wall_loads<T, FORM, -1>(p, cf, zo, zmo, zpo, x);
+            wall_combine<T, -1>(cf, x, g);
+            wall_loads<T, FORM, 0>(p, cf, zo, zmo, zpo, x);
+            wall_combine<T, 0>(cf, x, g);
+            wall_loads<T, FORM, 1>(p, cf, zo, zmo, zpo, x);
+            wall_combine<T, 1>(cf, x, g);
+        }
+    }
 }
 
 // two-buffer store: g*_i(x) into slot i of node x of the other buffer

@@ -102,7 +102,7 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
                                           long long n)
 {
     const int k = tc.k;
-    const Pull<T> p = make_pull(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
+    const Pull<T, WALL> p = make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
     const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const float sig = sigma_of(g, n);
@@ -126,9 +126,11 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
     }
 }
 
+// (the FP32/FP16 interpolated-wall variants ask for the bounce-back variant's 4 waves
+// per SIMD: without the hint it lands one register above that budget)
 template <typename T, int BLOCK, bool WALL>
-__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step(const Geom g, const Tiles t, const T *__restrict__ src,
-                                                               T *__restrict__ dst, int step_off)
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) < 8 ? 4 : 1)))
+void k_step(const Geom g, const Tiles t, const T *__restrict__ src, T *__restrict__ dst, int step_off)
 {
     const TileCoord tc = decode_tile(t, BLOCK);
     if (tc.k >= g.ncol) return;
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     double psum[4] = {0, 0, 0, 0};
     int cnt = 0;
     if (active) {
-        const Pull<T> p = make_pull(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
+        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
         const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
         const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
         const unsigned xy = g.colxy[k];
