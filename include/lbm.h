@@ -89,8 +89,10 @@ typedef struct {
                              arithmetic, 2 FP64 adjoint state and arithmetic */
     int32_t block;        /* threads per block: 64, 128, 256 (0 = default) */
     int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
-    int32_t xcd_remap;    /* workgroup -> tile order: 0 dispatch order, 1 XCD-aware (neighbouring
-                             tiles on one XCD, sharing its L2) */
+    int32_t xcd_remap;    /* workgroup -> tile order (workgroups go round-robin to the 8 XCDs):
+                             0 dispatch order; 1 XCD x takes the x-th eighth of the tiles;
+                             G in 2..4096: XCD x takes every eighth chunk of G consecutive
+                             tiles (neighbouring tiles share one XCD's L2) */
 } lbm_config;
 
 /* Layout facts of a configuration (host only, no GPU needed). */
@@ -146,7 +148,7 @@ int lbm_step_persistent(lbm_ctx *ctx, int32_t n);
 
 /* Change the launch geometry of lbm_step and lbm_step_graph on a live
  * context: threads per block (64, 128, 256), z planes per thread (1..64),
- * tile order (xcd_remap 0 or 1), pipes per launch (1..batch) and step order
+ * tile order (xcd_remap 0..4096, as in lbm_config), pipes per launch (1..batch) and step order
  * (pipe_major 0: every step covers all pipes; 1: within one call, each group
  * of pipes_per_launch pipes runs all n steps before the next group, so a
  * small pipe's working set stays in the 256 MB Infinity Cache).  A value of

@@ -441,15 +441,25 @@ __device__ __forceinline__ R feq_dev(R dr, const Axis<R> &X, const Axis<R> &Y, c
     return wgt<R>(I) * (dr * (R(1) + pim1) + pim1);
 }
 
-// Workgroup -> tile.  remap != 0: consecutive tiles go to the same XCD
-// (workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2), so the partial lines shared by neighbouring tiles stay in one L2;
-// remap == 0: dispatch order (spreads neighbouring tiles over the XCDs).
+// Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs
+// (workgroup w runs on XCD w % 8), each with its own L2.  remap == 0:
+// dispatch order (neighbouring tiles on different XCDs); remap == 1: XCD x
+// takes the x-th eighth of the tiles; remap = G >= 2: XCD x takes every
+// eighth chunk of G consecutive tiles, so neighbouring tiles, which share
+// the partial lines of the shifted pull reads, stay in one L2 while the XCDs
+// still sweep the buffers together.  Tiles past the last whole round of 8
+// chunks keep dispatch order.
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks, int remap)
 {
     if (!remap) return bid;
-    const int q = nblocks >> 3, r = nblocks & 7, x = bid & 7, s = bid >> 3;
-    return x * q + (x < r ? x : r) + s;
+    const int x = bid & 7, s = bid >> 3;
+    if (remap == 1) {
+        const int q = nblocks >> 3, r = nblocks & 7;
+        return x * q + (x < r ? x : r) + s;
+    }
+    const int full = nblocks / (8 * remap) * (8 * remap);
+    if (bid >= full) return bid;
+    return ((s / remap) * 8 + x) * remap + s % remap;
 }
 
 }  // namespace lbm

@@ -116,7 +116,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.elem = c.storage == 1 ? 2 : (c.storage == 2 ? 8 : 4);
     const long long pipe_elems = 27LL * c.nz * L.P;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
-    if (c.xcd_remap != 0 && c.xcd_remap != 1) return bad("xcd_remap must be 0 or 1");
+    if (c.xcd_remap < 0 || c.xcd_remap > 4096) return bad("xcd_remap must be in 0..4096");
     L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap, 0, c.batch};
     L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1, 0, c.batch};
     L.n_sigma = c.n_modes > 0 ? std::max<long long>(c.force_off_step, 0) : 0;
@@ -544,7 +544,7 @@ int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap,
     if (pipe_major < -1 || pipe_major > 1) return fail(c, LBM_EINVAL, "pipe_major must be -1, 0 or 1");
     if (block && block != 64 && block != 128 && block != 256) return fail(c, LBM_EINVAL, "block must be 64, 128 or 256");
     if (zchunk && (zchunk < 1 || zchunk > 64)) return fail(c, LBM_EINVAL, "zchunk must be in 1..64");
-    if (xcd_remap < -1 || xcd_remap > 1) return fail(c, LBM_EINVAL, "xcd_remap must be -1, 0 or 1");
+    if (xcd_remap < -1 || xcd_remap > 4096) return fail(c, LBM_EINVAL, "xcd_remap must be in -1..4096");
     if (ppl < 0 || ppl > c->cfg.batch) return fail(c, LBM_EINVAL, "pipes_per_launch must be in 0..batch");
     Tiles &t = c->L.step;
     if (block) {
