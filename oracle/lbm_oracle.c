@@ -330,6 +330,11 @@ static double wall_fraction(const orc_config *c, int x, int y, int d)
     return (-bb + sqrt(bb * bb - 4.0 * aa * cc)) / (2.0 * aa);
 }
 
+double orc_wall_fraction(const orc_config *c, int32_t x, int32_t y, int32_t d)
+{
+    return wall_fraction(c, x, y, d);
+}
+
 /* Terms of the streaming step, Eq. (streaming), for population i at fluid
  * node (x,y,z): f_i(x, n+1) = sum_t coef[t] * fs_{pop[t]}(src[t], n).
  * Shared by the forward stream and its exact transpose. */

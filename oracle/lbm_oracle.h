@@ -53,6 +53,10 @@ void orc_collide_cplx(const double f[54], const double a[6], double omega, doubl
  * (own node, incoming direction) and f*_out(x_ff); has_ff = 0 falls back to
  * halfway bounce-back. */
 double orc_bouzidi(double delta, double fs_out_x, double fs_in_x, double fs_out_xff, int32_t has_ff);
+/* Fraction Delta in (0, 1] of the link from fluid node (x, y) along the
+ * in-plane part of direction d at which it meets the wall r = R (ray-circle
+ * intersection), as used by the streaming with the Bouzidi wall. */
+double orc_wall_fraction(const orc_config *cfg, int32_t x, int32_t y, int32_t d);
 /* Trigger force of Eq. (TurbForce) summed over modes, at a point, with the
  * time factor sin(2 pi t / T) taken as 1; Cartesian components. */
 void orc_trigger_shape(const orc_config *cfg, const double *amps, double x, double y, double z,

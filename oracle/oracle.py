@@ -64,6 +64,8 @@ def lib():
         L.orc_collide_cplx.argtypes = [dp, dp, C.c_double, dp]
         L.orc_bouzidi.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32]
         L.orc_bouzidi.restype = C.c_double
+        L.orc_wall_fraction.argtypes = [cfgp, C.c_int32, C.c_int32, C.c_int32]
+        L.orc_wall_fraction.restype = C.c_double
         L.orc_trigger_shape.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_force_at.argtypes = [cfgp, dp, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp]
         L.orc_pipe_new.argtypes = [cfgp, dp]
@@ -184,6 +186,11 @@ def collide_complex(f, a, omega):
 def bouzidi(delta, fs_out_x, fs_in_x, fs_out_xff, has_ff=True):
     return lib().orc_bouzidi(float(delta), float(fs_out_x), float(fs_in_x), float(fs_out_xff),
                              int(bool(has_ff)))
+
+
+def wall_fraction(cfg: OrcConfig, x, y, d):
+    """Delta of the link from fluid node (x, y) along direction d to r = R."""
+    return lib().orc_wall_fraction(C.byref(cfg), int(x), int(y), int(d))
 
 
 def trigger_shape(cfg: OrcConfig, amps, x, y, z):

@@ -265,6 +265,34 @@ def test_bouzidi_reduces_to_halfway_bounce_back_at_half(O):
     assert O.bouzidi(0.2, 0.3, 0.7, 0.11, has_ff=False) == 0.3
 
 
+def test_wall_fraction_is_the_ray_circle_intersection(O):
+    """Delta along +x from (x, y): (px + Delta)^2 + py^2 = R^2 in closed form;
+    along a diagonal the point p + Delta (1, 1) lies on the circle; the
+    fraction is in (0, 1] exactly for links that cross the wall."""
+    cfg = O.make_config(nx=24, ny=24, nz=1, radius=10.0)
+    c, _, _ = O.lattice()
+    xc = yc = 11.5
+    d_px = [i for i in range(27) if tuple(c[i]) == (1, 0, 0)][0]
+    d_diag = [i for i in range(27) if tuple(c[i]) == (1, 1, 0)][0]
+    mask = O.Pipe(cfg).fluid_mask()[0]
+    n_cut = 0
+    for y in range(24):
+        for x in range(24):
+            if not mask[y, x]:
+                continue
+            px, py = x - xc, y - yc
+            if not mask[y, x + 1]:
+                n_cut += 1
+                delta = O.wall_fraction(cfg, x, y, d_px)
+                assert abs(delta - (np.sqrt(100.0 - py * py) - px)) < 1e-12
+                assert 0.0 < delta <= 1.0
+            if not mask[y + 1, x + 1]:
+                delta = O.wall_fraction(cfg, x, y, d_diag)
+                assert abs((px + delta) ** 2 + (py + delta) ** 2 - 100.0) < 1e-9
+                assert 0.0 < delta <= 1.0
+    assert n_cut > 10
+
+
 def test_halfway_streaming_is_a_permutation(O):
     """Pull streaming with halfway bounce-back and periodic wrap maps the
     post-collision populations one-to-one onto the new populations."""
