@@ -73,12 +73,12 @@ def _events(stream):
     return a, b
 
 
-def leg_fp16(steps=500, storage=1, pattern=0, wall=0):
+def leg_fp16(steps=500, storage=1, pattern=0, wall=0, preset="turbulent"):
     """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
     import torch
     import lbm_inputs as LI
     import paper_2405_12082_amd as P
-    cfg = LI.preset("turbulent")
+    cfg = LI.preset(preset)
     cfg["storage"] = storage
     cfg["pattern"] = pattern
     cfg["wall"] = wall
@@ -117,6 +117,14 @@ def leg_bouzidi(steps=500):
     (fbc1)/(fbc2) instead of the halfway bounce-back."""
     r = leg_fp16(steps, storage=0, pattern=0, wall=1)
     r["wall"] = "interpolated (Bouzidi)"
+    return r
+
+
+def leg_paper(steps=300):
+    """The paper's own pipe, 300x300x600 (R = 149.5), FP32, with its wall
+    (the interpolation of Eqs. (fbc1)/(fbc2)) and its k_theta = 2 trigger."""
+    r = leg_fp16(steps, storage=0, pattern=0, wall=1, preset="paper")
+    r["workload"] = "paper pipe 300x300x600 R=149.5, interpolated wall"
     return r
 
 
@@ -306,7 +314,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,aa,bouzidi,batched,adjoint,precision",
+    ap.add_argument("--legs", default="fp16,aa,bouzidi,paper,batched,adjoint,precision",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -435,7 +443,8 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     for leg in legs:
-        extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "batched": leg_batched,
+        extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "paper": leg_paper,
+                      "batched": leg_batched,
                       "adjoint": leg_adjoint,
                       "precision": leg_precision}[leg]()
     if extra:

@@ -23,6 +23,8 @@ PAPER_RE_TAU = 181.3
 PAPER_RE_BULK = 5329.3
 PAPER_RADIUS = 149.5
 PAPER_GRID = (300, 300, 600)
+PAPER_K_THETA = 2   # azimuthal wavenumber of the trigger force
+PAPER_A0 = 50.0     # trigger-force amplitude in units of h
 #: bulk-to-friction velocity ratio implied by the printed Reynolds numbers:
 #: Re = U_b (2R) / nu and Re_tau = u* R / nu give U_b / u* = Re / (2 Re_tau).
 BULK_OVER_UTAU = PAPER_RE_BULK / (2.0 * PAPER_RE_TAU)
@@ -185,6 +187,11 @@ def preset(name: str) -> dict:
     if name == "batched":  # 64 pipes of 64x64x256, R=30, nu = 0.0032
         return _pipe(64, 64, 256, 30.0, PAPER_NU, PAPER_U_TAU, batch=64, force_off_step=5000,
                      steps=5000)
+    if name == "paper":  # the paper's pipe (Section II.B): 300x300x600, R = 149.5, Bouzidi wall,
+        # one trigger mode k_theta = 2 (cos) of amplitude h A_0 for the first 3 T^LET, 30 T^LET in all
+        t_let = round(PAPER_RADIUS / PAPER_U_TAU)
+        return _pipe(*PAPER_GRID, PAPER_RADIUS, PAPER_NU, PAPER_U_TAU, n_modes=PAPER_K_THETA,
+                     force_off_step=3 * t_let, steps=30 * t_let, wall=1, paper_A0=PAPER_A0)
     if name == "adjoint":  # 96x96x384, R=45, nu = 0.0032, J over steps 1501..2000
         return _pipe(96, 96, 384, 45.0, PAPER_NU, PAPER_U_TAU, force_off_step=2000, steps=2000,
                      obs_begin=1501, obs_end=2001, checkpoint_every=100)
@@ -192,7 +199,12 @@ def preset(name: str) -> dict:
 
 
 def preset_amplitudes(cfg: dict) -> np.ndarray:
-    """[batch][2*n_modes] amplitudes for a preset (seed, seed+1, ...)."""
+    """[batch][2*n_modes] amplitudes for a preset (seed, seed+1, ...).  The
+    paper's pipe has one cosine mode k_theta = n_modes of amplitude h A_0."""
+    if "paper_A0" in cfg:
+        a = np.zeros((int(cfg.get("batch", 1)), 2 * int(cfg["n_modes"])))
+        a[:, 2 * (int(cfg["n_modes"]) - 1)] = float(cfg["paper_A0"]) * float(cfg["accel_z"])
+        return a
     return batch_amplitudes(int(cfg.get("seed", 0)), int(cfg.get("batch", 1)),
                             int(cfg["n_modes"]), float(cfg["u_tau"]), float(cfg["period"]))
 

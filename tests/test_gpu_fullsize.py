@@ -1,7 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
 times (needs an MI355X).
 
-* The turbulent pipe 192x192x1152 (R = 90): one fused step from seeded random
+* The turbulent pipe 192x192x1152 (R = 90) and the paper's pipe 300x300x600
+  (R = 149.5, interpolated wall): one fused step from seeded random
   deviations with the trigger force active; every population of ~400
   sampled nodes (wall-adjacent columns, both periodic z ends, the last
   columns of the layout, random interior nodes) against the FP64 oracle's
@@ -38,15 +39,19 @@ def _log(msg):
 SEED, AMP = 2024, 0.02
 
 
-def test_turbulent_pipe_one_step_sampled_parity(P, oracle_mod):
-    O = oracle_mod
-    cfg = LI.preset("turbulent")
+def _sampled_step_parity(P, O, name, s):
+    """One fused step of preset ``name`` from seeded random deviations at step
+    s, in the default launch geometry (as bench.py); ~400 sampled nodes (wall
+    columns, both periodic z ends, the last columns of the layout, random
+    interior nodes), every population against the FP64 oracle's collide +
+    stream computed node by node (halfway bounce-back or, wall = 1, the
+    interpolation of Eqs. (fbc1)/(fbc2) with the oracle's wall fraction)."""
+    cfg = LI.preset(name)
     amps = LI.preset_amplitudes(cfg)
     nx, ny, nz = LI.dims_of(cfg)
-    s = 301  # sin(2 pi s / T) ~ 1 with T = 1206: trigger force at full strength
     ocfg = O.make_config(**cfg)
     mask2d = O.Pipe(O.make_config(**dict(cfg, nz=1))).fluid_mask()[0]
-    _log(f"full-size parity: {nx}x{ny}x{nz}, {int(mask2d.sum())} fluid columns")
+    _log(f"full-size parity ({name}, wall {cfg['wall']}): {nx}x{ny}x{nz}, {int(mask2d.sum())} fluid columns")
 
     pipe = P.Pipe(cfg, amps)  # default launch geometry, as bench.py
     g = LI.random_deviations_torch(SEED, (nz, ny, nx), AMP)
@@ -98,7 +103,17 @@ def test_turbulent_pipe_one_step_sampled_parity(P, oracle_mod):
         own = collided(x, y, z)
         for i in range(27):
             sx, sy, sz = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
-            expect[n, i] = (collided(sx, sy, sz)[i] if mask2d[sy, sx] else own[opp[i]]) - w[i]
+            if mask2d[sy, sx]:
+                v = collided(sx, sy, sz)[i]
+            elif cfg["wall"] == 0:
+                v = own[opp[i]]
+            else:
+                delta = O.wall_fraction(ocfg, x, y, opp[i])
+                fx_, fy_, fz_ = (x + c[i, 0]) % nx, (y + c[i, 1]) % ny, (z + c[i, 2]) % nz
+                has_ff = bool(mask2d[fy_, fx_])
+                far = collided(fx_, fy_, fz_)[opp[i]] if has_ff else 0.0
+                v = O.bouzidi(delta, own[opp[i]], own[i], far, has_ff)
+            expect[n, i] = v - w[i]
     px = torch.as_tensor(pick[:, 0], device="cuda")
     py = torch.as_tensor(pick[:, 1], device="cuda")
     pz = torch.as_tensor(pick[:, 2], device="cuda")
@@ -108,6 +123,17 @@ def test_turbulent_pipe_one_step_sampled_parity(P, oracle_mod):
     err = np.abs(got - expect).max()
     _log(f"{len(pick)} sampled nodes x 27 populations: max abs error {err:.3e} (tolerance {tol:.3e})")
     assert err <= tol
+
+
+def test_turbulent_pipe_one_step_sampled_parity(P, oracle_mod):
+    # s = 301: sin(2 pi s / T) ~ 1 with T = 1206, trigger force at full strength
+    _sampled_step_parity(P, oracle_mod, "turbulent", 301)
+
+
+def test_paper_pipe_one_step_sampled_parity(P, oracle_mod):
+    """The paper's pipe, 300x300x600 (R = 149.5) with the interpolated wall
+    and its k_theta = 2 trigger mode; s = 501: sin(2 pi s / T) = 1 at T = 2004."""
+    _sampled_step_parity(P, oracle_mod, "paper", 501)
 
 
 def test_adjoint_pipe_gradient_vs_central_differences(P):

@@ -55,6 +55,19 @@ def test_presets_follow_the_paper_relations():
             assert abs(c["u_tau"] * 90.0 / nu - 181.3) < 1e-9
     t = LI.preset("turbulent")
     assert (t["nx"], t["ny"], t["nz"], t["radius"]) == (192, 192, 1152, 90.0)
+    # the paper's own pipe, Section II.B
+    g = json.load(open(GOLDEN))
+    p = LI.preset("paper")
+    nu = (p["tau"] - 0.5) / 3.0
+    assert [p["nx"], p["ny"], p["nz"]] == g["grid"] and p["radius"] == g["radius"] and p["wall"] == 1
+    assert abs(nu - g["nu"]) < 1e-15 and p["u_tau"] == g["u_tau"]
+    assert abs(math.sqrt(p["accel_z"] * p["radius"] / 2) - g["u_tau"]) < 1e-15
+    assert p["period"] == round(g["T_over_TLET"] * g["T_LET"])
+    assert p["force_off_step"] == 3 * g["T_LET"] and p["steps"] == 30 * g["T_LET"]
+    assert (p["kz"], p["kappa"], p["l0_frac"], p["l_frac"]) == (g["kz"], g["kappa"], g["l0_over_R"], g["l_over_R"])
+    a = LI.preset_amplitudes(p)
+    assert a.shape == (1, 2 * g["ktheta"]) and a[0, 2 * (g["ktheta"] - 1)] == g["A0"] * p["accel_z"]
+    assert np.count_nonzero(a) == 1
     assert LI.preset("batched")["batch"] == 64
 
 

@@ -25,6 +25,7 @@ def test_library_exports_every_header_function():
     ("precision_ref", 2828, 723968),
     ("batched", 2828, 723968),
     ("adjoint", 6376, 2448384),
+    ("paper", 70168, 42100800),
 ])
 def test_layout_counts_fluid_columns(name, ncol, nodes, oracle_mod):
     cfg = LI.preset(name)
