@@ -1,0 +1,49 @@
+"""The long-run driver (paper_2405_12082_amd.run): sampling schedule and
+radial statistics against u_z taken directly from the stepped state (needs
+an MI355X)."""
+import numpy as np
+import pytest
+
+import lbm_inputs as LI
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2405_12082_amd as P
+    P.lib()
+    return P
+
+
+def test_run_statistics_match_sampled_velocity(P):
+    from paper_2405_12082_amd import run
+    lines = []
+    res = run.run("precision_ref", 400, 200, every=100, progress=200, log=lines.append)
+    assert res["samples"] == 3 and len(lines) == 2
+    prof = res["profiles"]
+    cfg = LI.preset("precision_ref")
+    p = P.Pipe(cfg, LI.preset_amplitudes(cfg))
+    nx, ny, nz = LI.dims_of(cfg)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(xx - 0.5 * (nx - 1), yy - 0.5 * (ny - 1))
+    fluid = r < cfg["radius"]
+    nb = len(prof["r"])
+    idx = np.minimum(r.astype(int), nb - 1)
+    s1 = np.zeros(nb)
+    cnt = np.zeros(nb)
+    for target in (200, 300, 400):
+        p.step(target - p.step_index)
+        uz = p.moments()[1][0, 2].cpu().numpy().astype(np.float64)  # [nz][ny][nx]
+        for b in range(nb):
+            sel = fluid & (idx == b)
+            s1[b] += uz[:, sel].sum()
+            cnt[b] += nz * sel.sum()
+    mean = np.where(cnt > 0, s1 / np.maximum(cnt, 1), 0.0)
+    np.testing.assert_allclose(prof["count"], cnt)
+    np.testing.assert_allclose(prof["mean"], mean, rtol=1e-6, atol=1e-9)
+    nu = (cfg["tau"] - 0.5) / 3.0
+    np.testing.assert_allclose(prof["y_plus"], (cfg["radius"] - np.asarray(prof["r"])) * cfg["u_tau"] / nu)
