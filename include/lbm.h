@@ -251,6 +251,32 @@ int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *
 int lbm_stream_copy(lbm_ctx *ctx, int32_t n);
 
 /* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
+/* Coherent-structure identification, Section II.C.
+ *
+ * lbm_ring_sample: the streamwise velocity u_z (as lbm_moments reports it,
+ * at the current step) on the circle r = r0 (lattice units; the paper uses
+ * r0 = 0.78 R) at ntheta points theta_j = 2 pi j / ntheta, theta =
+ * atan2(y - y_c, x - x_c), by bilinear interpolation of the four
+ * surrounding nodes, for every plane z of every pipe.  ring: device
+ * [batch][nz][ntheta] float.  Async (the first call for a new (r0, ntheta)
+ * synchronises the stream once).  LBM_EINVAL for ntheta outside 4..4096,
+ * r0 <= 0, or a ring that touches a solid node.
+ *
+ * lbm_ring_spectrum: for each plane the Fourier transform of the azimuthal
+ * correlation R_uu(dtheta) = <du(theta0) du(theta0 + dtheta)>_theta0 / u_rms^2
+ * of the ring samples (du about the plane's ring mean), which equals the
+ * normalised power |U(m)|^2 / sum_j du_j^2 of the DFT U of du, for modes
+ * m = 0..mmax (m = 0 is 0): spec, device [batch][nz][mmax+1] double.
+ * mean (device [batch][mmax+1] double, may be NULL): the plane average;
+ * dominant (device [batch] int32, may be NULL; needs mean): the dominant
+ * azimuthal mode, the highest peak of the power of the averaged transform
+ * among m >= 1 (0 if it vanishes).  ring: as written by lbm_ring_sample
+ * (ntheta per plane).  Async.  LBM_EINVAL for NULL ring/spec, ntheta
+ * outside 4..4096, mmax outside 1..ntheta/2, dominant without mean. */
+int lbm_ring_sample(lbm_ctx *ctx, double r0, int32_t ntheta, float *ring);
+int lbm_ring_spectrum(lbm_ctx *ctx, const float *ring, int32_t ntheta, int32_t mmax, double *spec, double *mean,
+                      int32_t *dominant);
+
 const char *lbm_last_error(const lbm_ctx *ctx);
 /* Release the context (not the caller's memory).  Synchronises its stream. */
 void lbm_destroy(lbm_ctx *ctx);

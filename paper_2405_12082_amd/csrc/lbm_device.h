@@ -441,6 +441,34 @@ __device__ __forceinline__ R feq_dev(R dr, const Axis<R> &X, const Axis<R> &Y, c
     return wgt<R>(I) * (dr * (R(1) + pim1) + pim1);
 }
 
+// ---------------------------------------------------------------- forcing
+// time factor sigma(n) = sin(2 pi n / T) of the trigger force, 0 once it is off
+__device__ __forceinline__ float sigma_of(const Geom &g, long long n)
+{
+    return (n >= 0 && n < g.n_sigma) ? g.sigma[n] : 0.f;
+}
+
+__device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : z - 1; }
+__device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
+
+// body acceleration a(x, n) = h z^ + sigma(n) (C_z P_x, C_z P_y, S_z Q), in the
+// arithmetic type (FP32 tables promoted for FP64 storage)
+template <typename R>
+__device__ __forceinline__ void body_force(const Geom &g, int z, float sig, float px, float py, float pq, R &ax, R &ay,
+                                           R &az)
+{
+    const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
+    if constexpr (sizeof(R) == 4) {
+        ax = sig * cz * px;
+        ay = sig * cz * py;
+        az = g.accel_z + sig * sz * pq;
+    } else {
+        ax = R(sig) * R(cz) * R(px);
+        ay = R(sig) * R(cz) * R(py);
+        az = R(g.accel_z) + R(sig) * R(sz) * R(pq);
+    }
+}
+
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs
 // (workgroup w runs on XCD w % 8), each with its own L2.  remap == 0:
 // dispatch order (neighbouring tiles on different XCDs); remap == 1: XCD x

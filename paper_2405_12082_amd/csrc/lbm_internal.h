@@ -59,6 +59,14 @@ struct ObserveArgs {
     double *energy_part;// [tiles]
 };
 
+// ring of the coherent-structure sampling: four nodes (columns) and bilinear
+// weights per ring point
+struct RingArgs {
+    const int *col;     // [ntheta][4]
+    const double *w;    // [ntheta][4]
+    int ntheta;
+};
+
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
@@ -76,6 +84,12 @@ hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, 
                           int step_off, hipStream_t s);
 hipError_t launch_init(int storage, int form, const Geom &g, const float *u0, void *state, hipStream_t s);
 hipError_t launch_set_pops(int storage, int form, const Geom &g, const float *pops, void *state, hipStream_t s);
+hipError_t launch_ring(int storage, int form, const Geom &g, const RingArgs &r, const void *state, float *ring,
+                       hipStream_t s);
+hipError_t launch_ring_spectrum(const float *ring, int planes, int n, int mmax, const double *tw, double *spec,
+                                hipStream_t s);
+hipError_t launch_spectrum_mean(const double *spec, int B, int nz, int mmax, double *mean, int *dominant,
+                                hipStream_t s);
 hipError_t launch_reduce_diag(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
 hipError_t launch_reduce_energy(const Geom &g, const Tiles &t, const double *part, double *out, hipStream_t s);
 hipError_t launch_accumulate_energy(const Geom &g, const Tiles &t, const double *part, double scale, double *acc,

@@ -38,13 +38,6 @@ __device__ __forceinline__ void load_columns(const Geom &g, int k, int (&col)[9]
     for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
 }
 
-__device__ __forceinline__ float sigma_of(const Geom &g, long long n)
-{
-    return (n >= 0 && n < g.n_sigma) ? g.sigma[n] : 0.f;
-}
-
-__device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : z - 1; }
-__device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
 // ---------------------------------------------------------------- step
 // LBM_WAVES_PER_EU (compile time) asks the compiler for a register budget
@@ -57,24 +50,6 @@ __device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : 
 #else
 #define LBM_OCCUPANCY
 #endif
-
-// body acceleration a(x, n) = h z^ + sigma(n) (C_z P_x, C_z P_y, S_z Q), in the
-// arithmetic type (FP32 tables promoted for FP64 storage)
-template <typename R>
-__device__ __forceinline__ void body_force(const Geom &g, int z, float sig, float px, float py, float pq, R &ax, R &ay,
-                                           R &az)
-{
-    const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
-    if constexpr (sizeof(R) == 4) {
-        ax = sig * cz * px;
-        ay = sig * cz * py;
-        az = g.accel_z + sig * sz * pq;
-    } else {
-        ax = R(sig) * R(cz) * R(px);
-        ay = R(sig) * R(cz) * R(py);
-        az = R(g.accel_z) + R(sig) * R(sz) * R(pq);
-    }
-}
 
 // Step variants: the two-buffer pattern (read FORM_S from src, aligned store
 // into dst) and the in-place AA pattern (even n: read own slots, store

@@ -25,6 +25,7 @@ namespace {
 constexpr int kMaxModes = 6;
 constexpr long long kMaxSigma = 1LL << 24;   // longest forcing window (steps)
 constexpr int kObsZChunk = 16;               // z planes per thread for observation kernels
+constexpr int kMaxRing = 4096;               // ring points of the coherent-structure sampling
 constexpr int kDefaultBlock = 256;
 // default z planes per thread by storage (measured on the 192^2 x 1152 pipe:
 // FP32 1.173 ms at 1 plane vs 1.209 ms at 4; FP16 best at 8)
@@ -43,6 +44,7 @@ struct Layout {
     size_t off_state[2], off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
+    size_t off_ring_col, off_ring_w, off_twiddle;
     size_t total = 0;
     long long n_sigma = 0;
     std::string err;
@@ -140,6 +142,9 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
     L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
+    L.off_ring_col = take((size_t)kMaxRing * 4 * sizeof(int));
+    L.off_ring_w = take((size_t)kMaxRing * 4 * sizeof(double));
+    L.off_twiddle = take((size_t)kMaxRing * 2 * sizeof(double));
     const size_t obs_tiles = (size_t)L.obs.count() * B;
     L.off_diag_part = take(obs_tiles * 5 * sizeof(double));
     L.off_diag_out = take(B * 5 * sizeof(double));
@@ -225,6 +230,12 @@ struct lbm_ctx {
     long long cursor = -1, obs_begin = 0, obs_end = 0;
     int lam_cur = 0;
     bool lam_nonzero = false;
+    // coherent-structure ring: host copies of the device tables (alive while
+    // their asynchronous uploads run) and what they were built for
+    std::vector<int> ring_col;
+    std::vector<double> ring_w, twiddle;
+    double ring_r0 = -1.0;
+    int ring_n = 0, tw_n = 0;
 
     void *state(long long n) const { return ws + L.off_state[n & 1]; }
     // form of the buffer that holds the state of step n
@@ -807,6 +818,74 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
         c->lam_cur ^= 1;
         c->cursor -= 1;
     }
+    return LBM_OK;
+}
+
+int lbm_ring_sample(lbm_ctx *c, double r0, int32_t ntheta, float *ring)
+{
+    CHECK_CTX(c);
+    if (!ring || ntheta < 4 || ntheta > kMaxRing || !(r0 > 0.0))
+        return fail(c, LBM_EINVAL, "lbm_ring_sample: need ring != NULL, 4 <= ntheta <= 4096, r0 > 0");
+    if (!(c->cfg.radius > 0.0)) return fail(c, LBM_EINVAL, "lbm_ring_sample: needs a pipe wall (radius > 0)");
+    if (r0 != c->ring_r0 || ntheta != c->ring_n) {
+        const int nx = c->cfg.nx, ny = c->cfg.ny;
+        const double xc = 0.5 * (nx - 1), yc = 0.5 * (ny - 1);
+        c->ring_col.assign((size_t)ntheta * 4, 0);
+        c->ring_w.assign((size_t)ntheta * 4, 0.0);
+        for (int j = 0; j < ntheta; ++j) {
+            const double th = 2.0 * M_PI * j / ntheta;
+            const double px = xc + r0 * std::cos(th), py = yc + r0 * std::sin(th);
+            const int x0 = (int)std::floor(px), y0 = (int)std::floor(py);
+            const double fx = px - x0, fy = py - y0;
+            const int xs[4] = {x0, x0 + 1, x0, x0 + 1}, ys[4] = {y0, y0, y0 + 1, y0 + 1};
+            const double ws[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+            for (int q = 0; q < 4; ++q) {
+                const int col = (xs[q] >= 0 && xs[q] < nx && ys[q] >= 0 && ys[q] < ny)
+                                    ? c->L.colmap[(size_t)ys[q] * nx + xs[q]] : -1;
+                if (col < 0) {
+                    c->ring_r0 = -1.0;
+                    return fail(c, LBM_EINVAL, "lbm_ring_sample: the ring touches a solid node (r0 too large)");
+                }
+                c->ring_col[(size_t)j * 4 + q] = col;
+                c->ring_w[(size_t)j * 4 + q] = ws[q];
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_col, c->ring_col.data(), c->ring_col.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_w, c->ring_w.data(), c->ring_w.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));  // the host tables may be rebuilt by the next call
+        c->ring_r0 = r0;
+        c->ring_n = ntheta;
+    }
+    const RingArgs r{(const int *)(c->ws + c->L.off_ring_col), (const double *)(c->ws + c->L.off_ring_w), ntheta};
+    HIPCHK(c, launch_ring(c->cfg.storage, c->form(c->step), c->geom, r, c->state(c->step), ring, c->stream));
+    return LBM_OK;
+}
+
+int lbm_ring_spectrum(lbm_ctx *c, const float *ring, int32_t ntheta, int32_t mmax, double *spec, double *mean,
+                      int32_t *dominant)
+{
+    CHECK_CTX(c);
+    if (!ring || !spec || ntheta < 4 || ntheta > kMaxRing || mmax < 1 || mmax > ntheta / 2 || (dominant && !mean))
+        return fail(c, LBM_EINVAL,
+                    "lbm_ring_spectrum: need ring, spec != NULL, 4 <= ntheta <= 4096, 1 <= mmax <= ntheta/2, "
+                    "mean when dominant is requested");
+    if (ntheta != c->tw_n) {
+        c->twiddle.assign((size_t)ntheta * 2, 0.0);
+        for (int q = 0; q < ntheta; ++q) {
+            const double a = 2.0 * M_PI * q / ntheta;
+            c->twiddle[2 * q] = std::cos(a);
+            c->twiddle[2 * q + 1] = -std::sin(a);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_twiddle, c->twiddle.data(), c->twiddle.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->tw_n = ntheta;
+    }
+    HIPCHK(c, launch_ring_spectrum(ring, c->cfg.batch * c->cfg.nz, ntheta, mmax,
+                                   (const double *)(c->ws + c->L.off_twiddle), spec, c->stream));
+    if (mean) HIPCHK(c, launch_spectrum_mean(spec, c->cfg.batch, c->cfg.nz, mmax, mean, dominant, c->stream));
     return LBM_OK;
 }
 

@@ -1,0 +1,173 @@
+// lbm_structures.hip -- coherent-structure identification on the GPU
+// (arXiv:2405.12082, Section II.C): the streamwise velocity on the circle
+// r = r0, the Fourier transform of its azimuthal correlation
+// R_uu(r0, dtheta) = < u_z(theta0) u_z(theta0 + dtheta) >_theta0 / u_rms^2 per
+// cross-section, the plane average, and the dominant azimuthal mode.
+//
+// By the Wiener-Khinchin relation the transform of the circular correlation
+// of one plane is |U(m)|^2 / sum_j du_j^2, U the DFT of the fluctuation du
+// (about the ring mean), so a plane costs one DFT of its N ring samples.
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// u_z at ring point j of plane z of pipe b: bilinear interpolation of the
+// macroscopic velocity u_z = j_z / rho + a_z / 2 of the four surrounding
+// nodes (Eq. (macroscopic_u), as lbm_moments reports it), the nodes' values
+// gathered from the state like the step does.  FP64 interpolation.
+template <typename T, int FORM, bool WALL>
+__global__ __launch_bounds__(256) void k_ring(const Geom g, const RingArgs r, const T *__restrict__ state, float *ring)
+{
+    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long total = (long long)g.B * g.nz * r.ntheta;
+    if (idx >= total) return;
+    const int j = (int)(idx % r.ntheta);
+    const long long rest = idx / r.ntheta;
+    const int z = (int)(rest % g.nz), b = (int)(rest / g.nz);
+    using R = typename RealOf<T>::type;
+    const float sig = sigma_of(g, *g.step_dev);
+    const unsigned rowb = (unsigned)g.P * sizeof(T);
+    const unsigned zo = (unsigned)z * rowb, zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
+    double acc = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+        const int col = r.col[j * 4 + q];
+        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col, g.bcoef);
+        R v[27];
+        gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
+        const float *fs = g.fshape + (size_t)b * 3 * g.P;
+        R ax, ay, az;
+        body_force<R>(g, z, sig, fs[col], fs[g.P + col], fs[2 * g.P + col], ax, ay, az);
+        const Moments<R> m = moments_of<R>(v);
+        const R uz = m.jz * rcp_r(R(1) + m.dr) + R(0.5) * az;
+        acc += r.w[j * 4 + q] * (double)uz;
+    }
+    ring[idx] = (float)acc;
+}
+
+// One block per (pipe, plane): fluctuation about the ring mean, then the
+// normalised power |U(m)|^2 / sum du^2 for m = 1..mmax (m = 0 is 0), FP64,
+// twiddles exp(-2 pi i q / N) from a table.
+__global__ __launch_bounds__(256) void k_ring_spectrum(const float *__restrict__ ring, int n, int mmax,
+                                                       const double *__restrict__ tw, double *__restrict__ spec)
+{
+    __shared__ double u[4096];
+    __shared__ double red[256];
+    const int plane = blockIdx.x;
+    const float *rz = ring + (size_t)plane * n;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        u[j] = (double)rz[j];
+        s += u[j];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double mean = red[0] / n;
+    __syncthreads();
+    double e = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) {
+        u[j] -= mean;
+        e += u[j] * u[j];
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double energy = red[0];
+    double *out = spec + (size_t)plane * (mmax + 1);
+    if (threadIdx.x == 0) out[0] = 0.0;
+    for (int m = 1 + threadIdx.x; m <= mmax; m += 256) {
+        double re = 0.0, im = 0.0;
+        int q = 0;  // (m j) mod n
+        for (int j = 0; j < n; ++j) {
+            re += u[j] * tw[2 * q];
+            im += u[j] * tw[2 * q + 1];
+            q += m;
+            if (q >= n) q -= n;
+        }
+        out[m] = energy > 0.0 ? (re * re + im * im) / energy : 0.0;
+    }
+}
+
+// One block per pipe: plane average of the spectra (fixed order) and the
+// dominant mode, the highest peak among m >= 1 (first on ties; 0 when the
+// spectrum vanishes).
+__global__ __launch_bounds__(256) void k_spectrum_mean(const double *__restrict__ spec, int nz, int mmax,
+                                                       double *__restrict__ mean, int *__restrict__ dominant)
+{
+    const int b = blockIdx.x;
+    double *mb = mean + (size_t)b * (mmax + 1);
+    for (int m = threadIdx.x; m <= mmax; m += 256) {
+        double s = 0.0;
+        for (int z = 0; z < nz; ++z) s += spec[((size_t)b * nz + z) * (mmax + 1) + m];
+        mb[m] = s / nz;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && dominant) {
+        int best = 0;
+        double top = 0.0;
+        for (int m = 1; m <= mmax; ++m) {
+            const double p = mb[m] * mb[m];
+            if (p > top) {
+                top = p;
+                best = m;
+            }
+        }
+        dominant[b] = best;
+    }
+}
+
+template <typename T, int FORM, bool WALL>
+static void ring_t(const Geom &g, const RingArgs &r, const void *state, float *ring, hipStream_t s)
+{
+    const long long total = (long long)g.B * g.nz * r.ntheta;
+    hipLaunchKernelGGL((k_ring<T, FORM, WALL>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, r,
+                       (const T *)state, ring);
+}
+template <typename T>
+static void ring_form(int form, const Geom &g, const RingArgs &r, const void *state, float *ring, hipStream_t s)
+{
+    if (form == FORM_N)
+        ring_t<T, FORM_N, false>(g, r, state, ring, s);
+    else if (form == FORM_W)
+        ring_t<T, FORM_W, false>(g, r, state, ring, s);
+    else if (g.bcoef)
+        ring_t<T, FORM_S, true>(g, r, state, ring, s);
+    else
+        ring_t<T, FORM_S, false>(g, r, state, ring, s);
+}
+
+hipError_t launch_ring(int storage, int form, const Geom &g, const RingArgs &r, const void *state, float *ring,
+                       hipStream_t s)
+{
+    if (storage == 2)
+        ring_form<double>(form, g, r, state, ring, s);
+    else if (storage == 1)
+        ring_form<__half>(form, g, r, state, ring, s);
+    else
+        ring_form<float>(form, g, r, state, ring, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_spectrum(const float *ring, int planes, int n, int mmax, const double *tw, double *spec,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ring_spectrum, dim3(planes), dim3(256), 0, s, ring, n, mmax, tw, spec);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum_mean(const double *spec, int B, int nz, int mmax, double *mean, int *dominant,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_spectrum_mean, dim3(B), dim3(256), 0, s, spec, nz, mmax, mean, dominant);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -164,6 +164,28 @@ class Pipe:
                     "lbm_profile_read")
         return out
 
+    # ------------------------------------------------------------ coherent structures
+    def ring_sample(self, r0: float, ntheta: int = 1024, out: torch.Tensor | None = None) -> torch.Tensor:
+        """u_z on the circle r = r0 at ntheta angles, every plane of every pipe:
+        float32 [batch][nz][ntheta] on the device."""
+        if out is None:
+            out = torch.empty((self.cfg.batch, self.cfg.nz, int(ntheta)), dtype=torch.float32, device=self.device)
+        self._check(self.lib.lbm_ring_sample(self._ctx, float(r0), int(ntheta), C.c_void_p(_ptr(out))),
+                    "lbm_ring_sample")
+        return out
+
+    def ring_spectrum(self, ring: torch.Tensor, mmax: int = 64):
+        """Transform of the azimuthal correlation per plane ([batch][nz][mmax+1]),
+        its plane average ([batch][mmax+1]) and the dominant mode ([batch])."""
+        B, nz, n = ring.shape
+        spec = torch.empty((B, nz, mmax + 1), dtype=torch.float64, device=self.device)
+        mean = torch.empty((B, mmax + 1), dtype=torch.float64, device=self.device)
+        dom = torch.empty((B,), dtype=torch.int32, device=self.device)
+        self._check(self.lib.lbm_ring_spectrum(self._ctx, C.c_void_p(_ptr(ring)), int(n), int(mmax),
+                                               C.c_void_p(_ptr(spec)), C.c_void_p(_ptr(mean)),
+                                               C.c_void_p(_ptr(dom))), "lbm_ring_spectrum")
+        return spec, mean, dom
+
     # ------------------------------------------------------------ checkpoints
     @property
     def state_bytes(self) -> int:
