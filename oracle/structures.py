@@ -12,6 +12,10 @@ fluctuation is taken about the ring mean (which only touches the m = 0
 term); one correlation per z plane, averaged over the planes (the flow is
 homogeneous along the pipe).  Everything is written out literally:
 correlation by the sum over theta0, its transform by the DFT sum.
+
+Section III: the series of dominant modes, its transition matrix, the
+Chapman-Kolmogorov test on decimated series and the self mode correlation
+function, written as loops over the series.
 """
 import numpy as np
 
@@ -73,10 +77,58 @@ def dominant_mode(spectrum):
 
 
 def transition_matrix(modes, lag, n_states):
-    """T[i][j] = P(mode j at t + lag | mode i at t) from a sequence of
-    dominant modes (1..n_states); rows without visits stay zero."""
+    """T[i][j] = P(mode i at t + lag | mode j at t), columns summing to 1 as
+    in the printed matrix of Section III (its columns sum to 1 within
+    rounding, its rows do not), from a sequence of dominant modes
+    (1..n_states); columns of modes never left stay zero."""
     t = np.zeros((n_states, n_states))
     for a, b in zip(modes[:-lag], modes[lag:]):
-        t[a - 1, b - 1] += 1
-    rows = t.sum(axis=1, keepdims=True)
-    return np.divide(t, rows, out=np.zeros_like(t), where=rows > 0)
+        t[b - 1, a - 1] += 1
+    cols = t.sum(axis=0, keepdims=True)
+    return np.divide(t, cols, out=np.zeros_like(t), where=cols > 0)
+
+
+def decimate(modes, order):
+    """The series sampled every order-th element (decimation of that order)."""
+    return list(modes[::order])
+
+
+def ck_eigenvalues(modes, n_states, orders):
+    """Chapman-Kolmogorov test: for each decimation order d, the eigenvalue
+    magnitudes of the transition matrix of the decimated series, and the
+    Markov prediction |lambda(T_1)|^d, both sorted in decreasing order."""
+    lam1 = np.sort(np.abs(np.linalg.eigvals(transition_matrix(modes, 1, n_states))))[::-1]
+    out = []
+    for d in orders:
+        lam = np.sort(np.abs(np.linalg.eigvals(transition_matrix(decimate(modes, d), 1, n_states))))[::-1]
+        out.append((lam, lam1 ** d))
+    return out
+
+
+def self_correlation(modes, n_states, max_lag):
+    """F_m(tau) = (<V_m(t) V_m(t + tau)> - <V_m>^2) / (same at tau = 0), V_m(t)
+    = 1 if the mode at t is m else 0, for m = 1..n_states and tau =
+    0..max_lag (averages over the available pairs); and their average over
+    the modes that occur."""
+    v = np.array([[1.0 if k == m else 0.0 for k in modes] for m in range(1, n_states + 1)])
+    f = np.zeros((n_states, max_lag + 1))
+    for m in range(n_states):
+        mean = v[m].mean()
+        for tau in range(max_lag + 1):
+            pairs = [v[m, t] * v[m, t + tau] for t in range(len(modes) - tau)]
+            f[m, tau] = np.mean(pairs) - mean * mean
+    occ = f[:, 0] > 0
+    fn = np.zeros_like(f)
+    fn[occ] = f[occ] / f[occ, :1]
+    return fn, fn[occ].mean(axis=0)
+
+
+def run_lengths(modes, n_states):
+    """Lengths (in samples) of the runs of consecutive equal modes, per mode."""
+    runs = {m: [] for m in range(1, n_states + 1)}
+    start = 0
+    for t in range(1, len(modes) + 1):
+        if t == len(modes) or modes[t] != modes[start]:
+            runs[modes[start]].append(t - start)
+            start = t
+    return runs

@@ -57,9 +57,61 @@ def test_spectrum_is_the_power_spectrum_of_the_fluctuation():
 
 
 def test_transition_matrix_counts():
+    """Columns are the current mode, rows the next one (the convention of
+    the printed matrix, whose columns sum to 1)."""
     t = S.transition_matrix([1, 2, 1, 2, 1, 1, 3], 1, 3)
-    np.testing.assert_allclose(t, [[1 / 4, 2 / 4, 1 / 4], [1, 0, 0], [0, 0, 0]])
+    np.testing.assert_allclose(t, np.array([[1 / 4, 2 / 4, 1 / 4], [1, 0, 0], [0, 0, 0]]).T)
     t2 = S.transition_matrix([1, 2, 1, 2, 1, 1, 3], 2, 3)
-    np.testing.assert_allclose(t2, [[2 / 3, 0, 1 / 3], [0.5, 0.5, 0], [0, 0, 0]])
+    np.testing.assert_allclose(t2, np.array([[2 / 3, 0, 1 / 3], [0.5, 0.5, 0], [0, 0, 0]]).T)
     with pytest.raises(IndexError):
         S.transition_matrix([1, 4], 1, 3)
+
+
+def test_transition_matrix_of_a_markov_chain_and_the_ck_prediction():
+    """A simulated 3-state Markov chain with a known column-stochastic T:
+    the estimate is within sampling error, and the decimated series obey
+    the Chapman-Kolmogorov relation |lambda(T_d)| = |lambda(T_1)|^d."""
+    T = np.array([[0.90, 0.05, 0.10], [0.06, 0.90, 0.05], [0.04, 0.05, 0.85]])
+    rng = np.random.default_rng(11)
+    s, modes = 0, []
+    for _ in range(200000):
+        modes.append(s + 1)
+        s = rng.choice(3, p=T[:, s])
+    est = S.transition_matrix(modes, 1, 3)
+    np.testing.assert_allclose(est, T, atol=0.01)
+    for lam, pred in S.ck_eigenvalues(modes, 3, (1, 2, 4)):
+        np.testing.assert_allclose(lam, pred, atol=0.02)
+    lam_true = np.sort(np.abs(np.linalg.eigvals(T)))[::-1]
+    np.testing.assert_allclose(S.ck_eigenvalues(modes, 3, (1,))[0][0], lam_true, atol=0.01)
+
+
+def test_self_correlation_closed_forms():
+    """Blocks of L equal modes cycling through all n modes: V_m is a periodic
+    indicator of period n L, whose normalised autocovariance at lag tau <= L
+    is ((L - tau)/(n L) - 1/n^2) / (1/n - 1/n^2) (exact for the full cycle
+    when the averages run over whole periods: checked on a long series)."""
+    n, L = 4, 10
+    modes = [1 + (t // L) % n for t in range(n * L * 400)]
+    f, mean = S.self_correlation(modes, n, L)
+    tau = np.arange(L + 1)
+    expect = ((L - tau) / (n * L) - 1 / n ** 2) / (1 / n - 1 / n ** 2)
+    for m in range(n):
+        np.testing.assert_allclose(f[m], expect, atol=2e-3)
+    np.testing.assert_allclose(mean, expect, atol=2e-3)
+
+
+def test_run_lengths():
+    runs = S.run_lengths([2, 2, 1, 3, 3, 3, 2], 3)
+    assert runs == {1: [1], 2: [2, 1], 3: [3]}
+    assert S.decimate([1, 2, 3, 4, 5, 6, 7], 3) == [1, 4, 7]
+
+
+def test_printed_transition_matrix_is_column_stochastic():
+    """The convention of transition_matrix: the printed matrix's columns sum
+    to 1 within its three-decimal rounding, its rows do not."""
+    import json
+    import os
+    t = np.array(json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                             "transition_matrix_printed.json")))["T"])
+    assert np.abs(t.sum(axis=0) - 1).max() <= 0.006
+    assert np.abs(t.sum(axis=1) - 1).max() > 0.05
