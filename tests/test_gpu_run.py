@@ -47,3 +47,24 @@ def test_run_statistics_match_sampled_velocity(P):
     np.testing.assert_allclose(prof["mean"], mean, rtol=1e-6, atol=1e-9)
     nu = (cfg["tau"] - 0.5) / 3.0
     np.testing.assert_allclose(prof["y_plus"], (cfg["radius"] - np.asarray(prof["r"])) * cfg["u_tau"] / nu)
+
+
+def test_run_records_the_dominant_mode_series(P):
+    """Modes every 20 steps from step 200 (11 samples): the series equals the
+    dominant modes found by sampling a second pipe at the same steps, and the
+    statistics are those of the host functions on that series."""
+    from paper_2405_12082_amd import run, structures as H
+    res = run.run("precision_ref", 400, 200, every=100, progress=200, log=lambda s: None, modes_every=20,
+                  modes_from=200, ntheta=256, mmax=10)
+    m = res["modes"]
+    assert len(m["series"]) == 11
+    cfg = LI.preset("precision_ref")
+    p = P.Pipe(cfg, LI.preset_amplitudes(cfg))
+    ref = []
+    for target in range(200, 401, 20):
+        p.step(target - p.step_index)
+        _, _, dom = p.ring_spectrum(p.ring_sample(0.78 * cfg["radius"], 256), 10)
+        ref.append(int(dom.cpu()[0]))
+    assert m["series"] == ref
+    if min(ref) >= 1:
+        np.testing.assert_allclose(m["transition_matrix"], H.transition_matrix(ref, 10))
