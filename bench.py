@@ -120,11 +120,36 @@ def leg_bouzidi(steps=500):
     return r
 
 
-def leg_paper(steps=300):
+def leg_paper(steps=300, ntheta=1024, mmax=10, reps=50):
     """The paper's own pipe, 300x300x600 (R = 149.5), FP32, with its wall
-    (the interpolation of Eqs. (fbc1)/(fbc2)) and its k_theta = 2 trigger."""
+    (the interpolation of Eqs. (fbc1)/(fbc2)) and its k_theta = 2 trigger;
+    plus the cost of one coherent-structure sample (Section II.C: u_z on
+    r = 0.78 R at every plane, transform of the azimuthal correlation,
+    dominant mode)."""
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
     r = leg_fp16(steps, storage=0, pattern=0, wall=1, preset="paper")
     r["workload"] = "paper pipe 300x300x600 R=149.5, interpolated wall"
+    cfg = LI.preset("paper")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        p = P.Pipe(cfg, LI.preset_amplitudes(cfg), stream=stream)
+        p.step(200)
+        ring = p.ring_sample(0.78 * cfg["radius"], ntheta)
+        p.ring_spectrum(ring, mmax)
+        a, b = _events(stream)
+        a.record(stream)
+        for _ in range(reps):
+            p.ring_sample(0.78 * cfg["radius"], ntheta, out=ring)
+            _, _, dom = p.ring_spectrum(ring, mmax)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+        del p
+        torch.cuda.empty_cache()
+    r["structure_sample"] = {"ms": round(ms, 4), "ntheta": ntheta, "planes": cfg["nz"], "mmax": mmax,
+                             "per_step_equivalent": round(ms / r["ms_per_step"], 4)}
     return r
 
 
@@ -310,6 +335,7 @@ def main():
     ap.add_argument("--workload", default="turbulent")
     ap.add_argument("--storage", type=int, default=0, help="0: FP32, 1: FP16 deviations")
     ap.add_argument("--pattern", type=int, default=0, help="0: two buffers, 1: AA in place")
+    ap.add_argument("--wall", type=int, default=None, help="0: halfway bounce-back, 1: interpolated (default: the workload's)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
@@ -351,6 +377,8 @@ def main():
     cfg = LI.preset(args.workload)
     cfg["storage"] = args.storage
     cfg["pattern"] = args.pattern
+    if args.wall is not None:
+        cfg["wall"] = args.wall
     cfg["block"] = args.block
     cfg["zchunk"] = args.zchunk
     cfg["xcd_remap"] = args.xcd_remap
@@ -411,7 +439,7 @@ def main():
     kavg_ms = float(np.mean(kern_ms)) if kern_ms else float("nan")
     alg_bytes = nf * cfg["batch"] * bpu
     achieved = alg_bytes / (kavg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage) if args.pattern == 0 else None
+    traffic = measured_traffic(args.workload, args.storage) if args.pattern == 0 and cfg["wall"] == 0 else None
     out = {
         "metric": "MLUPS + % HBM roofline (D3Q27 MRT fwd); adjoint/fwd cost ratio",
         "value": round(mlups, 1),
@@ -428,6 +456,8 @@ def main():
         "config": {"workload": f"{args.workload} pipe {cfg['nx']}x{cfg['ny']}x{cfg['nz']} R={cfg['radius']}",
                    "fluid_nodes": nf, "batch": cfg["batch"], "storage": "fp32" if args.storage == 0 else "fp16",
                    "tau": round(cfg["tau"], 6), "n_modes": cfg["n_modes"], "force_off_step": cfg["force_off_step"],
+                   "wall": ["halfway bounce-back", "interpolated (Bouzidi)"][cfg["wall"]],
+                   "pattern": ["two buffers", "AA in place"][cfg["pattern"]],
                    "sample_every": SAMPLE_EVERY, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
