@@ -87,7 +87,7 @@ typedef struct {
     double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
     int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state and
                              arithmetic, 2 FP64 adjoint state and arithmetic */
-    int32_t block;        /* threads per block: 64, 128, 256 (0 = default) */
+    int32_t block;        /* threads per block: 64, 128, 256, 512 (0 = default) */
     int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
     int32_t xcd_remap;    /* workgroup -> tile order (workgroups go round-robin to the 8 XCDs):
                              0 dispatch order; 1 XCD x takes the x-th eighth of the tiles;
@@ -147,7 +147,7 @@ int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
 int lbm_step_persistent(lbm_ctx *ctx, int32_t n);
 
 /* Change the launch geometry of lbm_step and lbm_step_graph on a live
- * context: threads per block (64, 128, 256), z planes per thread (1..64),
+ * context: threads per block (64, 128, 256, 512), z planes per thread (1..64),
  * tile order (xcd_remap 0..4096, as in lbm_config), pipes per launch (1..batch) and step order
  * (pipe_major 0: every step covers all pipes; 1: within one call, each group
  * of pipes_per_launch pipes runs all n steps before the next group, so a

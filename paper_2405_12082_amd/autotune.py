@@ -30,7 +30,7 @@ def _key(pipe) -> str:
 def candidates(batch: int):
     ppl = sorted({batch, max(1, batch // 2), max(1, batch // 4), max(1, batch // 8), 1}, reverse=True)
     orders = (0, 1) if batch > 1 else (0,)
-    for block, zchunk, xcd, p, pm in itertools.product((64, 128, 256), (1, 2, 4, 8, 16), (0, 1, 8), ppl, orders):
+    for block, zchunk, xcd, p, pm in itertools.product((64, 128, 256, 512), (1, 2, 4, 8, 16), (0, 1, 8), ppl, orders):
         if pm == 1 and p == batch:
             continue  # one group: both orders are the same launch sequence
         yield dict(block=block, zchunk=zchunk, xcd_remap=xcd, pipes_per_launch=p, pipe_major=pm)

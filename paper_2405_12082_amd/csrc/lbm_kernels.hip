@@ -564,6 +564,9 @@ static hipError_t step_wall(const Geom &g, const Tiles &t, const void *src, void
     case 128:
         hipLaunchKernelGGL((k_step<T, 128, WALL>), grid, dim3(128), 0, s, g, t, (const T *)src, (T *)dst, off);
         break;
+    case 512:
+        hipLaunchKernelGGL((k_step<T, 512, WALL>), grid, dim3(512), 0, s, g, t, (const T *)src, (T *)dst, off);
+        break;
     default:
         hipLaunchKernelGGL((k_step<T, 256, WALL>), grid, dim3(256), 0, s, g, t, (const T *)src, (T *)dst, off);
         break;
@@ -600,6 +603,7 @@ static hipError_t step_aa_block(const Geom &g, const Tiles &t, void *buf, int of
     switch (t.block) {
     case 64: step_aa_t<T, 64, MODE>(g, t, buf, off, s); break;
     case 128: step_aa_t<T, 128, MODE>(g, t, buf, off, s); break;
+    case 512: step_aa_t<T, 512, MODE>(g, t, buf, off, s); break;
     default: step_aa_t<T, 256, MODE>(g, t, buf, off, s); break;
     }
     return hipGetLastError();
@@ -635,6 +639,7 @@ static hipError_t persistent_block(const Geom &g, const Tiles &t, void *b0, void
     switch (t.block) {
     case 64: return persistent_t<T, 64, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
     case 128: return persistent_t<T, 128, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 512: return persistent_t<T, 512, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
     default: return persistent_t<T, 256, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
     }
 }
@@ -670,8 +675,10 @@ template <typename T, int BLOCK, bool AA, bool WALL> static int occ_t()
 }
 template <typename T, bool AA, bool WALL> static int occ_block(int block)
 {
-    return block == 64 ? occ_t<T, 64, AA, WALL>()
-                       : (block == 128 ? occ_t<T, 128, AA, WALL>() : occ_t<T, 256, AA, WALL>());
+    return block == 64    ? occ_t<T, 64, AA, WALL>()
+           : block == 128 ? occ_t<T, 128, AA, WALL>()
+           : block == 512 ? occ_t<T, 512, AA, WALL>()
+                          : occ_t<T, 256, AA, WALL>();
 }
 template <typename T> static int occ_pattern(int aa, int wall, int block)
 {

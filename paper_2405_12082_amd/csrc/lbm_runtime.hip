@@ -93,7 +93,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
         return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
     const int block = c.block ? c.block : kDefaultBlock;
-    if (block != 64 && block != 128 && block != 256) return bad("block must be 64, 128 or 256");
+    if (block != 64 && block != 128 && block != 256 && block != 512) return bad("block must be 64, 128, 256 or 512");
     const int zchunk = c.zchunk ? c.zchunk : kDefaultZChunk[(c.storage >= 0 && c.storage <= 2) ? c.storage : 0];
     if (zchunk < 1 || zchunk > 64) return bad("zchunk must be in 1..64");
 
@@ -553,7 +553,8 @@ int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap,
 {
     CHECK_CTX(c);
     if (pipe_major < -1 || pipe_major > 1) return fail(c, LBM_EINVAL, "pipe_major must be -1, 0 or 1");
-    if (block && block != 64 && block != 128 && block != 256) return fail(c, LBM_EINVAL, "block must be 64, 128 or 256");
+    if (block && block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(c, LBM_EINVAL, "block must be 64, 128, 256 or 512");
     if (zchunk && (zchunk < 1 || zchunk > 64)) return fail(c, LBM_EINVAL, "zchunk must be in 1..64");
     if (xcd_remap < -1 || xcd_remap > 4096) return fail(c, LBM_EINVAL, "xcd_remap must be in -1..4096");
     if (ppl < 0 || ppl > c->cfg.batch) return fail(c, LBM_EINVAL, "pipes_per_launch must be in 0..batch");

@@ -80,7 +80,7 @@ def test_autotune_restores_state_and_caches(P, tmp_path):
 
 def test_set_launch_rejects_bad_values(P):
     p = P.Pipe(_cfg(batch=2), _amps(_cfg(batch=2)))
-    for bad in (dict(block=96), dict(zchunk=65), dict(xcd_remap=4097), dict(pipes_per_launch=3),
+    for bad in (dict(block=1024), dict(zchunk=65), dict(xcd_remap=4097), dict(pipes_per_launch=3),
                 dict(pipe_major=2)):
         with pytest.raises(P.LbmError):
             p.set_launch(**bad)
