@@ -579,17 +579,26 @@ static hipError_t step_t(const Geom &g, const Tiles &t, const void *src, void *d
     return g.bcoef ? step_wall<T, true>(g, t, src, dst, off, s) : step_wall<T, false>(g, t, src, dst, off, s);
 }
 
-hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
+// the copy runs in the step's tiles: its block size must be the step's
+template <typename T>
+static hipError_t copy_t(const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
 {
     const dim3 grid(grid_of(t));
-    if (storage == 2)
-        hipLaunchKernelGGL((k_stream_copy<double, 256>), grid, dim3(256), 0, s, g, t, (const double *)src, (double *)dst);
-    else if (storage == 1)
-        hipLaunchKernelGGL((k_stream_copy<unsigned short, 256>), grid, dim3(256), 0, s, g, t, (const unsigned short *)src,
-                           (unsigned short *)dst);
-    else
-        hipLaunchKernelGGL((k_stream_copy<float, 256>), grid, dim3(256), 0, s, g, t, (const float *)src, (float *)dst);
+    const T *a = (const T *)src;
+    T *b = (T *)dst;
+    switch (t.block) {
+    case 64: hipLaunchKernelGGL((k_stream_copy<T, 64>), grid, dim3(64), 0, s, g, t, a, b); break;
+    case 128: hipLaunchKernelGGL((k_stream_copy<T, 128>), grid, dim3(128), 0, s, g, t, a, b); break;
+    case 512: hipLaunchKernelGGL((k_stream_copy<T, 512>), grid, dim3(512), 0, s, g, t, a, b); break;
+    default: hipLaunchKernelGGL((k_stream_copy<T, 256>), grid, dim3(256), 0, s, g, t, a, b); break;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s)
+{
+    if (storage == 2) return copy_t<double>(g, t, src, dst, s);
+    return storage == 1 ? copy_t<unsigned short>(g, t, src, dst, s) : copy_t<float>(g, t, src, dst, s);
 }
 
 template <typename T, int BLOCK, int MODE>
