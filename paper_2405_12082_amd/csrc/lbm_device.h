@@ -183,11 +183,14 @@ __device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typenam
     constexpr int d = NSLOT(-cx, -cy);
     if constexpr (d != 4 && cz == ZC) {
         constexpr int here = FORM == FORM_W ? OPP(I) : I;
-        const bool own_mode = cf[d] > 0;
-        const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
-        const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
-        x[I] = own_mode ? Codec<T>::template ld<I>(p.base + here * p.pbytes, off)
-                        : Codec<T>::template ld<I>(p.base + OPP(here) * p.pbytes, off);
+        // only the lanes with a cut link load (fluid slots keep x = 0, c = 1)
+        x[I] = 0;
+        if (p.wall & (1u << d)) {
+            const bool own_mode = cf[d] > 0;
+            const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
+            const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
+            x[I] = Codec<T>::template ld<I>(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off);
+        }
     }
     if constexpr (I + 1 < 27) wall_loads<T, FORM, ZC, I + 1>(p, cf, zo, zmo, zpo, x);
 }

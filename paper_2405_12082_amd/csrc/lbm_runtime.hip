@@ -27,8 +27,10 @@ constexpr long long kMaxSigma = 1LL << 24;   // longest forcing window (steps)
 constexpr int kObsZChunk = 16;               // z planes per thread for observation kernels
 constexpr int kMaxRing = 4096;               // ring points of the coherent-structure sampling
 // default threads per block by storage (turbulent pipe, graph replays: FP32
-// 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256)
+// 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256); the interpolated
+// wall is best at 256 threads and 2 planes (1.244 ms vs 1.281 at 512)
 constexpr int kDefaultBlock[3] = {512, 256, 256};
+constexpr int kDefaultBlockWall = 256, kDefaultZChunkWall = 2;
 // default z planes per thread by storage (measured on the 192^2 x 1152 pipe:
 // FP32 1.173 ms at 1 plane vs 1.209 ms at 4; FP16 best at 8)
 constexpr int kDefaultZChunk[3] = {1, 8, 2};
@@ -95,9 +97,10 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
         return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
     const int sidx = (c.storage >= 0 && c.storage <= 2) ? c.storage : 0;
-    const int block = c.block ? c.block : kDefaultBlock[sidx];
+    const bool wall_fp32 = c.wall == 1 && c.storage == 0;
+    const int block = c.block ? c.block : (wall_fp32 ? kDefaultBlockWall : kDefaultBlock[sidx]);
     if (block != 64 && block != 128 && block != 256 && block != 512) return bad("block must be 64, 128, 256 or 512");
-    const int zchunk = c.zchunk ? c.zchunk : kDefaultZChunk[sidx];
+    const int zchunk = c.zchunk ? c.zchunk : (wall_fp32 ? kDefaultZChunkWall : kDefaultZChunk[sidx]);
     if (zchunk < 1 || zchunk > 64) return bad("zchunk must be in 1..64");
 
     L.colmap.assign((size_t)c.nx * c.ny, -1);
