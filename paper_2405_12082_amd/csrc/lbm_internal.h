@@ -59,12 +59,14 @@ struct ObserveArgs {
     double *energy_part;// [tiles]
 };
 
-// ring of the coherent-structure sampling: four nodes (columns) and bilinear
-// weights per ring point
+// ring of the coherent-structure sampling: the distinct nodes (columns) it
+// touches, and per ring point the indices of its four nodes in that list and
+// their bilinear weights
 struct RingArgs {
-    const int *col;     // [ntheta][4]
+    const int *nodes;   // [n_nodes] columns
+    const int *idx;     // [ntheta][4] into nodes
     const double *w;    // [ntheta][4]
-    int ntheta;
+    int n_nodes, ntheta;
 };
 
 // launchers (return the hipError_t of the launch)

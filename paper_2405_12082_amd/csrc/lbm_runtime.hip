@@ -48,7 +48,7 @@ struct Layout {
     size_t off_state[2], off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
-    size_t off_ring_col, off_ring_w, off_twiddle;
+    size_t off_ring_nodes, off_ring_idx, off_ring_w, off_twiddle;
     size_t total = 0;
     long long n_sigma = 0;
     std::string err;
@@ -148,7 +148,8 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
     L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
-    L.off_ring_col = take((size_t)kMaxRing * 4 * sizeof(int));
+    L.off_ring_nodes = take((size_t)kMaxRing * 4 * sizeof(int));
+    L.off_ring_idx = take((size_t)kMaxRing * 4 * sizeof(int));
     L.off_ring_w = take((size_t)kMaxRing * 4 * sizeof(double));
     L.off_twiddle = take((size_t)kMaxRing * 2 * sizeof(double));
     const size_t obs_tiles = (size_t)L.obs.count() * B;
@@ -238,7 +239,7 @@ struct lbm_ctx {
     bool lam_nonzero = false;
     // coherent-structure ring: host copies of the device tables (alive while
     // their asynchronous uploads run) and what they were built for
-    std::vector<int> ring_col;
+    std::vector<int> ring_nodes, ring_idx;
     std::vector<double> ring_w, twiddle;
     double ring_r0 = -1.0;
     int ring_n = 0, tw_n = 0;
@@ -837,8 +838,10 @@ int lbm_ring_sample(lbm_ctx *c, double r0, int32_t ntheta, float *ring)
     if (r0 != c->ring_r0 || ntheta != c->ring_n) {
         const int nx = c->cfg.nx, ny = c->cfg.ny;
         const double xc = 0.5 * (nx - 1), yc = 0.5 * (ny - 1);
-        c->ring_col.assign((size_t)ntheta * 4, 0);
+        c->ring_nodes.clear();
+        c->ring_idx.assign((size_t)ntheta * 4, 0);
         c->ring_w.assign((size_t)ntheta * 4, 0.0);
+        std::vector<int> slot(c->L.ncol, -1);  // column -> index in ring_nodes
         for (int j = 0; j < ntheta; ++j) {
             const double th = 2.0 * M_PI * j / ntheta;
             const double px = xc + r0 * std::cos(th), py = yc + r0 * std::sin(th);
@@ -853,11 +856,17 @@ int lbm_ring_sample(lbm_ctx *c, double r0, int32_t ntheta, float *ring)
                     c->ring_r0 = -1.0;
                     return fail(c, LBM_EINVAL, "lbm_ring_sample: the ring touches a solid node (r0 too large)");
                 }
-                c->ring_col[(size_t)j * 4 + q] = col;
+                if (slot[col] < 0) {
+                    slot[col] = (int)c->ring_nodes.size();
+                    c->ring_nodes.push_back(col);
+                }
+                c->ring_idx[(size_t)j * 4 + q] = slot[col];
                 c->ring_w[(size_t)j * 4 + q] = ws[q];
             }
         }
-        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_col, c->ring_col.data(), c->ring_col.size() * sizeof(int),
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_nodes, c->ring_nodes.data(),
+                                 c->ring_nodes.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_idx, c->ring_idx.data(), c->ring_idx.size() * sizeof(int),
                                  hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->ws + c->L.off_ring_w, c->ring_w.data(), c->ring_w.size() * sizeof(double),
                                  hipMemcpyHostToDevice, c->stream));
@@ -865,7 +874,8 @@ int lbm_ring_sample(lbm_ctx *c, double r0, int32_t ntheta, float *ring)
         c->ring_r0 = r0;
         c->ring_n = ntheta;
     }
-    const RingArgs r{(const int *)(c->ws + c->L.off_ring_col), (const double *)(c->ws + c->L.off_ring_w), ntheta};
+    const RingArgs r{(const int *)(c->ws + c->L.off_ring_nodes), (const int *)(c->ws + c->L.off_ring_idx),
+                     (const double *)(c->ws + c->L.off_ring_w), (int)c->ring_nodes.size(), ntheta};
     HIPCHK(c, launch_ring(c->cfg.storage, c->form(c->step), c->geom, r, c->state(c->step), ring, c->stream));
     return LBM_OK;
 }

@@ -12,38 +12,39 @@
 
 namespace lbm {
 
-// u_z at ring point j of plane z of pipe b: bilinear interpolation of the
-// macroscopic velocity u_z = j_z / rho + a_z / 2 of the four surrounding
-// nodes (Eq. (macroscopic_u), as lbm_moments reports it), the nodes' values
-// gathered from the state like the step does.  FP64 interpolation.
+// One block per (pipe, plane): u_z = j_z / rho + a_z / 2 (Eq.
+// (macroscopic_u), as lbm_moments reports it) at each distinct node the
+// ring touches, gathered from the state like the step does, into LDS; then
+// every ring point by bilinear interpolation of its four nodes (FP64).
+constexpr int kRingNodes = 16384;  // 4 x the largest ring
 template <typename T, int FORM, bool WALL>
 __global__ __launch_bounds__(256) void k_ring(const Geom g, const RingArgs r, const T *__restrict__ state, float *ring)
 {
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    const long long total = (long long)g.B * g.nz * r.ntheta;
-    if (idx >= total) return;
-    const int j = (int)(idx % r.ntheta);
-    const long long rest = idx / r.ntheta;
-    const int z = (int)(rest % g.nz), b = (int)(rest / g.nz);
+    __shared__ float uz[kRingNodes];
+    const int z = blockIdx.x % g.nz, b = blockIdx.x / g.nz;
     using R = typename RealOf<T>::type;
     const float sig = sigma_of(g, *g.step_dev);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const unsigned zo = (unsigned)z * rowb, zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
-    double acc = 0.0;
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-        const int col = r.col[j * 4 + q];
+    const float *fs = g.fshape + (size_t)b * 3 * g.P;
+    for (int u = threadIdx.x; u < r.n_nodes; u += 256) {
+        const int col = r.nodes[u];
         const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col, g.bcoef);
         R v[27];
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
-        const float *fs = g.fshape + (size_t)b * 3 * g.P;
         R ax, ay, az;
         body_force<R>(g, z, sig, fs[col], fs[g.P + col], fs[2 * g.P + col], ax, ay, az);
         const Moments<R> m = moments_of<R>(v);
-        const R uz = m.jz * rcp_r(R(1) + m.dr) + R(0.5) * az;
-        acc += r.w[j * 4 + q] * (double)uz;
+        uz[u] = (float)(m.jz * rcp_r(R(1) + m.dr) + R(0.5) * az);
     }
-    ring[idx] = (float)acc;
+    __syncthreads();
+    float *out = ring + ((size_t)b * g.nz + z) * r.ntheta;
+    for (int j = threadIdx.x; j < r.ntheta; j += 256) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc += r.w[j * 4 + q] * (double)uz[r.idx[j * 4 + q]];
+        out[j] = (float)acc;
+    }
 }
 
 // One block per (pipe, plane): fluctuation about the ring mean, then the
@@ -96,20 +97,27 @@ __global__ __launch_bounds__(256) void k_ring_spectrum(const float *__restrict__
     }
 }
 
-// One block per pipe: plane average of the spectra (fixed order) and the
-// dominant mode, the highest peak among m >= 1 (first on ties; 0 when the
-// spectrum vanishes).
+// One block per pipe: plane average of the spectra (a fixed-order tree over
+// the planes) and the dominant mode, the highest peak among m >= 1 (first on
+// ties; 0 when the spectrum vanishes).
 __global__ __launch_bounds__(256) void k_spectrum_mean(const double *__restrict__ spec, int nz, int mmax,
                                                        double *__restrict__ mean, int *__restrict__ dominant)
 {
+    __shared__ double red[256];
     const int b = blockIdx.x;
     double *mb = mean + (size_t)b * (mmax + 1);
-    for (int m = threadIdx.x; m <= mmax; m += 256) {
+    for (int m = 0; m <= mmax; ++m) {
         double s = 0.0;
-        for (int z = 0; z < nz; ++z) s += spec[((size_t)b * nz + z) * (mmax + 1) + m];
-        mb[m] = s / nz;
+        for (int z = threadIdx.x; z < nz; z += 256) s += spec[((size_t)b * nz + z) * (mmax + 1) + m];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) mb[m] = red[0] / nz;
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0 && dominant) {
         int best = 0;
         double top = 0.0;
@@ -127,9 +135,8 @@ __global__ __launch_bounds__(256) void k_spectrum_mean(const double *__restrict_
 template <typename T, int FORM, bool WALL>
 static void ring_t(const Geom &g, const RingArgs &r, const void *state, float *ring, hipStream_t s)
 {
-    const long long total = (long long)g.B * g.nz * r.ntheta;
-    hipLaunchKernelGGL((k_ring<T, FORM, WALL>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, r,
-                       (const T *)state, ring);
+    hipLaunchKernelGGL((k_ring<T, FORM, WALL>), dim3((unsigned)(g.B * g.nz)), dim3(256), 0, s, g, r, (const T *)state,
+                       ring);
 }
 template <typename T>
 static void ring_form(int form, const Geom &g, const RingArgs &r, const void *state, float *ring, hipStream_t s)
