@@ -25,6 +25,10 @@ namespace {
 constexpr int kMaxModes = 6;
 constexpr long long kMaxSigma = 1LL << 24;   // longest forcing window (steps)
 constexpr int kObsZChunk = 16;               // z planes per thread for observation kernels
+#ifndef LBM_ADJ_ZCHUNK
+#define LBM_ADJ_ZCHUNK 8
+#endif
+constexpr int kAdjZChunk = LBM_ADJ_ZCHUNK;   // z planes per thread for the adjoint step
 constexpr int kMaxRing = 4096;               // ring points of the coherent-structure sampling
 // default threads per block by storage (turbulent pipe, graph replays: FP32
 // 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256); the interpolated
@@ -41,7 +45,7 @@ struct Layout {
     std::vector<int> colx, coly;   // fluid columns, row-major (y outer, x inner)
     std::vector<int> colmap;       // [ny][nx] -> column or -1
     int ncol = 0, P = 0;
-    Tiles step{}, obs{};
+    Tiles step{}, obs{}, adj{};
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
     // workspace offsets
@@ -127,6 +131,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.xcd_remap < 0 || c.xcd_remap > 4096) return bad("xcd_remap must be in 0..4096");
     L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap, 0, c.batch};
     L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1, 0, c.batch};
+    L.adj = Tiles{256, kAdjZChunk, (L.ncol + 255) / 256, (c.nz + kAdjZChunk - 1) / kAdjZChunk, 1, 0, c.batch};
     L.n_sigma = c.n_modes > 0 ? std::max<long long>(c.force_off_step, 0) : 0;
 
     size_t off = 0;
@@ -163,7 +168,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
         const size_t lam = align_up((size_t)pipe_elems * B * (c.adjoint == 2 ? sizeof(double) : sizeof(float)), 256);
         L.off_lam[0] = take(lam);
         L.off_lam[1] = take(lam);
-        L.off_grad_part = take(B * L.obs.nzc * P * 3 * sizeof(double));
+        L.off_grad_part = take(B * L.adj.nzc * P * 3 * sizeof(double));
         L.off_grad_col = take(B * P * 3 * sizeof(double));
         L.off_modes = take((size_t)2 * kMaxModes * 3 * P * sizeof(double));
     } else {
@@ -815,12 +820,12 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
         a.in_window = c->cursor >= c->obs_begin && c->cursor < c->obs_end;
         a.has_next = c->cursor + 1 < c->obs_end;
         a.energy_weight = wgt;
-        HIPCHK(c, launch_adjoint(c->cfg.storage, c->cfg.adjoint, c->geom, c->L.obs, a, c->stream));
+        HIPCHK(c, launch_adjoint(c->cfg.storage, c->cfg.adjoint, c->geom, c->L.adj, a, c->stream));
         if (nq > 0) {
             const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
             // the kernels use the FP32 table value of sigma; use the same rounding here
             const double sig32 = (double)(float)sig;
-            HIPCHK(c, launch_project_grad(c->geom, c->L.obs, a.grad_part, (double *)(c->ws + c->L.off_grad_col),
+            HIPCHK(c, launch_project_grad(c->geom, c->L.adj, a.grad_part, (double *)(c->ws + c->L.off_grad_col),
                                           (const double *)(c->ws + c->L.off_modes), nq, sig32, grad, c->stream));
         }
         c->lam_cur ^= 1;
