@@ -218,9 +218,13 @@ int lbm_load(lbm_ctx *ctx, const void *src, int64_t step);
  * states (lbm_save layout, device memory) f^{c-n+1} .. f^c in forward order,
  * state_stride bytes apart; they are consumed last to first, each one
  * producing lambda^c and moving the cursor to c - 1.  The gradient
- *     dJ/d amps[b][q] += sum_x [(dC/da)^T S^T lambda^{c+1} + dE_c/da] . da(x,c)/d amps[b][q]
- * is accumulated in FP64 into grad (device [batch][2*n_modes] doubles,
- * caller-owned, not zeroed).  Once f^0 is consumed the gradient is complete.
+ *     dJ/d amps[b][q] = sum_c sum_x [(dC/da)^T S^T lambda^{c+1} + dE_c/da] . da(x,c)/d amps[b][q]
+ * is accumulated in FP64 per column over the steps of the sweep (fixed
+ * order), and each call writes grad = (the values grad held at the sweep's
+ * first call) + the gradient of all steps consumed so far (device
+ * [batch][2*n_modes] doubles, caller-owned; not modified by the caller
+ * between the calls of one sweep), so the result does not depend on how the
+ * sweep is split into calls.  Once f^0 is consumed the gradient is complete.
  * Errors: LBM_ESTATE if the adjoint buffers are absent, no reset was made,
  * or the cursor would move below 0.  Async. */
 int lbm_adjoint_reset(lbm_ctx *ctx, int64_t obs_begin, int64_t obs_end);

@@ -246,9 +246,11 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     gp[2] = G[2];
 }
 
-// per-column sums over z-chunks (fixed order)
-__global__ __launch_bounds__(256) void k_grad_columns(const double *__restrict__ part, double *__restrict__ colsum,
-                                                      int nzc, int P, int ncol, int B)
+// acc[b][k] += sigma(n) * (sum over the z-chunks of step n's column partials),
+// fixed order: the force sensitivity of every column, summed over the steps
+// of the sweep so far
+__global__ __launch_bounds__(256) void k_grad_accumulate(const double *__restrict__ part, double *__restrict__ acc,
+                                                         int nzc, int P, int ncol, int B, double sigma)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (long long)B * ncol) return;
@@ -260,31 +262,32 @@ __global__ __launch_bounds__(256) void k_grad_columns(const double *__restrict__
         s[1] += p[1];
         s[2] += p[2];
     }
-    double *o = colsum + ((size_t)b * P + k) * 3;
-    o[0] = s[0];
-    o[1] = s[1];
-    o[2] = s[2];
+    double *o = acc + ((size_t)b * P + k) * 3;
+    o[0] += sigma * s[0];
+    o[1] += sigma * s[1];
+    o[2] += sigma * s[2];
 }
 
-// grad[b][q] += sigma * sum_k colsum[b][k] . shape_q(k), one block per (b, q)
-__global__ __launch_bounds__(256) void k_project(const double *__restrict__ colsum, const double *__restrict__ modes,
-                                                 int nq, int P, int ncol, double sigma, double *__restrict__ grad)
+// grad[b][q] = base[b][q] + sum_k acc[b][k] . shape_q(k), one block per (b, q)
+__global__ __launch_bounds__(256) void k_project(const double *__restrict__ acc, const double *__restrict__ modes,
+                                                 int nq, int P, int ncol, const double *__restrict__ base,
+                                                 double *__restrict__ grad)
 {
     __shared__ double lds[256];
     const int b = blockIdx.x / nq, q = blockIdx.x % nq;
-    double acc = 0.0;
+    double sum = 0.0;
     for (int k = threadIdx.x; k < ncol; k += 256) {
-        const double *cs = colsum + ((size_t)b * P + k) * 3;
-        acc += cs[0] * modes[((size_t)q * 3 + 0) * P + k] + cs[1] * modes[((size_t)q * 3 + 1) * P + k] +
+        const double *cs = acc + ((size_t)b * P + k) * 3;
+        sum += cs[0] * modes[((size_t)q * 3 + 0) * P + k] + cs[1] * modes[((size_t)q * 3 + 1) * P + k] +
                cs[2] * modes[((size_t)q * 3 + 2) * P + k];
     }
-    lds[threadIdx.x] = acc;
+    lds[threadIdx.x] = sum;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) grad[(size_t)b * nq + q] += sigma * lds[0];
+    if (threadIdx.x == 0) grad[(size_t)b * nq + q] = base[(size_t)b * nq + q] + lds[0];
 }
 
 template <typename T, typename R>
@@ -309,16 +312,19 @@ hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles
     return hipGetLastError();
 }
 
-hipError_t launch_project_grad(const Geom &g, const Tiles &t, const double *grad_part, double *colsum,
-                               const double *modes, int nq, double sigma, double *grad, hipStream_t s)
+hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
+                                  hipStream_t s)
 {
     const long long n = (long long)g.B * g.ncol;
-    hipLaunchKernelGGL(k_grad_columns, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, grad_part, colsum, t.nzc, g.P,
-                       g.ncol, g.B);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)(g.B * nq)), dim3(256), 0, s, colsum, modes, nq, g.P, g.ncol, sigma,
-                       grad);
+    hipLaunchKernelGGL(k_grad_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, grad_part, acc, t.nzc,
+                       g.P, g.ncol, g.B, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_grad(const Geom &g, const double *acc, const double *modes, int nq, const double *base,
+                               double *grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_project, dim3((unsigned)(g.B * nq)), dim3(256), 0, s, acc, modes, nq, g.P, g.ncol, base, grad);
     return hipGetLastError();
 }
 

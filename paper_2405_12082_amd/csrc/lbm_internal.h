@@ -114,7 +114,11 @@ struct AdjointArgs {
 };
 hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
                           hipStream_t s);
-hipError_t launch_project_grad(const Geom &g, const Tiles &t, const double *grad_part, double *colsum,
-                               const double *mode_shape, int nq, double sigma, double *grad, hipStream_t s);
+// acc[b][k] += sigma * column sums of the step's gradient partials
+hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
+                                  hipStream_t s);
+// grad[b][q] = base[b][q] + sum_k acc[b][k] . shape_q(k)
+hipError_t launch_project_grad(const Geom &g, const double *acc, const double *modes, int nq, const double *base,
+                               double *grad, hipStream_t s);
 
 }  // namespace lbm

@@ -51,7 +51,7 @@ struct Layout {
     // workspace offsets
     size_t off_state[2], off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
-    size_t off_lam[2], off_grad_part, off_grad_col, off_modes;
+    size_t off_lam[2], off_grad_part, off_grad_col, off_grad_base, off_modes;
     size_t off_ring_nodes, off_ring_idx, off_ring_w, off_twiddle;
     size_t total = 0;
     long long n_sigma = 0;
@@ -170,9 +170,10 @@ int build_layout(const lbm_config *cfg, Layout &L)
         L.off_lam[1] = take(lam);
         L.off_grad_part = take(B * L.adj.nzc * P * 3 * sizeof(double));
         L.off_grad_col = take(B * P * 3 * sizeof(double));
+        L.off_grad_base = take(B * 2 * kMaxModes * sizeof(double));
         L.off_modes = take((size_t)2 * kMaxModes * 3 * P * sizeof(double));
     } else {
-        L.off_lam[0] = L.off_lam[1] = L.off_grad_part = L.off_grad_col = L.off_modes = 0;
+        L.off_lam[0] = L.off_lam[1] = L.off_grad_part = L.off_grad_col = L.off_grad_base = L.off_modes = 0;
     }
     L.total = off;
     return LBM_OK;
@@ -242,6 +243,7 @@ struct lbm_ctx {
     long long cursor = -1, obs_begin = 0, obs_end = 0;
     int lam_cur = 0;
     bool lam_nonzero = false;
+    bool grad_base_set = false;  // the sweep's starting gradient has been saved
     // coherent-structure ring: host copies of the device tables (alive while
     // their asynchronous uploads run) and what they were built for
     std::vector<int> ring_nodes, ring_idx;
@@ -798,6 +800,8 @@ int lbm_adjoint_reset(lbm_ctx *c, int64_t obs_begin, int64_t obs_end)
     const size_t lam = (size_t)c->geom.pipe * c->cfg.batch * (c->cfg.adjoint == 2 ? sizeof(double) : sizeof(float));
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[0], lam, c->stream));
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[1], lam, c->stream));
+    HIPCHK(c, launch_fill(c->ws + c->L.off_grad_col, (size_t)c->cfg.batch * c->L.P * 3 * sizeof(double), c->stream));
+    c->grad_base_set = false;
     return LBM_OK;
 }
 
@@ -810,6 +814,12 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
     if (state_stride < c->L.state_bytes) return fail(c, LBM_EINVAL, "lbm_adjoint_step: state_stride < state size");
     const int nq = 2 * c->cfg.n_modes;
     const double wgt = 1.0 / ((double)(c->obs_end - c->obs_begin) * (double)c->L.ncol * c->cfg.nz);
+    double *acc = (double *)(c->ws + c->L.off_grad_col), *base = (double *)(c->ws + c->L.off_grad_base);
+    if (nq > 0 && !c->grad_base_set) {
+        HIPCHK(c, hipMemcpyAsync(base, grad, (size_t)c->cfg.batch * nq * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        c->grad_base_set = true;
+    }
     for (int j = n - 1; j >= 0; --j) {
         AdjointArgs a{};
         a.state = (const char *)fwd_states + (size_t)j * state_stride;
@@ -825,12 +835,13 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
             const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
             // the kernels use the FP32 table value of sigma; use the same rounding here
             const double sig32 = (double)(float)sig;
-            HIPCHK(c, launch_project_grad(c->geom, c->L.adj, a.grad_part, (double *)(c->ws + c->L.off_grad_col),
-                                          (const double *)(c->ws + c->L.off_modes), nq, sig32, grad, c->stream));
+            if (sig32 != 0.0) HIPCHK(c, launch_grad_accumulate(c->geom, c->L.adj, a.grad_part, acc, sig32, c->stream));
         }
         c->lam_cur ^= 1;
         c->cursor -= 1;
     }
+    if (nq > 0)
+        HIPCHK(c, launch_project_grad(c->geom, acc, (const double *)(c->ws + c->L.off_modes), nq, base, grad, c->stream));
     return LBM_OK;
 }
 
