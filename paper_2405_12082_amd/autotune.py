@@ -8,7 +8,7 @@ does not advance the simulation.  Results are cached in a JSON file keyed by
 the pipe shape, batch, storage, buffer pattern and GPU architecture.
 :func:`choose_pattern` tunes the two-buffer and the AA pattern of a
 configuration and returns the faster (the pattern is fixed when a context is
-created, so this builds one context per pattern).
+created, so it creates one context per pattern).
 """
 from __future__ import annotations
 

@@ -41,6 +41,7 @@ def _amps(cfg):
     dict(block=64, zchunk=3, xcd_remap=1, pipes_per_launch=2, pipe_major=0),
     dict(block=128, zchunk=20, xcd_remap=0, pipes_per_launch=1, pipe_major=1),
     dict(block=256, zchunk=1, xcd_remap=1, pipes_per_launch=3, pipe_major=1),
+    dict(block=512, zchunk=2, xcd_remap=8, pipes_per_launch=5, pipe_major=0),
 ])
 def test_launch_geometry_and_order_do_not_change_results(P, launch):
     cfg = _cfg()
@@ -86,7 +87,7 @@ def test_set_launch_rejects_bad_values(P):
             p.set_launch(**bad)
 
 
-@pytest.mark.parametrize("block,zchunk", [(256, 1), (64, 4)])
+@pytest.mark.parametrize("block,zchunk", [(256, 1), (64, 4), (512, 1)])
 def test_persistent_launch_equals_eager(P, block, zchunk):
     """One cooperative launch of n steps with a grid barrier between steps
     gives the same states as n ordinary launches (both buffer parities)."""

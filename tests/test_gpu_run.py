@@ -1,4 +1,4 @@
-"""The long-run driver (paper_2405_12082_amd.run): sampling schedule and
+"""Long runs (paper_2405_12082_amd.run): sampling schedule and
 radial statistics against u_z taken directly from the stepped state (needs
 an MI355X)."""
 import numpy as np
