@@ -1,10 +1,13 @@
 // lbm_device.h -- device-side building blocks of the D3Q27 MRT pipe stepper
-// for gfx950: lattice constants, storage codecs, the pull gather with
-// halfway bounce-back, and the per-node collision in deviation form.
+// for gfx950: lattice constants, storage codecs, the pull gather with the
+// halfway bounce-back or the interpolated wall and the stores of the
+// two-buffer and AA patterns, the per-node collision in deviation form, the
+// body force and the XCD-aware tile order.
 //
 // Method: arXiv:2405.12082, appendix (Eqs. (Mmatrix), (mrt), (lambda), (m*),
 // (Rmrti), (BoltzmannEquilibriumDistribution), (k*f*)) and Section II
-// (Eqs. (collision), (streaming), (macroscopic_rho), (macroscopic_u), (fbc1)).
+// (Eqs. (collision), (streaming), (macroscopic_rho), (macroscopic_u), (fbc1),
+// (fbc2), (TurbForce)).
 #pragma once
 
 #include <hip/hip_fp16.h>

@@ -7,7 +7,11 @@
 // 64 elements).  Between steps the buffer holds the post-collision values
 // g*(n-1) = S^T g(n) (S: streaming with the wall), so a step is one pull
 // gather, one collision and one aligned store per node: 27 loads and 27
-// stores, 216 B (FP32) or 108 B (FP16) of HBM traffic per fluid-node update.
+// stores, 216 B (FP32), 108 B (FP16) or 432 B (FP64) of HBM traffic per
+// fluid-node update.  The AA pattern keeps one buffer whose form alternates
+// with the step parity (see StateForm); multi-step launches (graphs, the
+// persistent kernel), observation of the state and the state writers live
+// here too.
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
