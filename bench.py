@@ -400,10 +400,16 @@ def main():
         ev_pairs = []
         t_start = torch.cuda.Event(enable_timing=True)
         t_end = torch.cuda.Event(enable_timing=True)
+        n_seg = 5 if args.steps >= 5 else 1  # five equal segments: median and spread
+        seg_ev = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         t_start.record(stream)
         for s in range(args.steps):
+            if s % (args.steps // n_seg) == 0 and len(seg_ev) < n_seg:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(stream)
+                seg_ev.append((s, e))
             if s % 10 == 5:  # bracket every tenth step kernel with events
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
@@ -419,6 +425,9 @@ def main():
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms_total = t_start.elapsed_time(t_end)
+        bounds = seg_ev + [(args.steps, t_end)]
+        seg_mlups = [nf * cfg["batch"] * (s1 - s0) / (e0.elapsed_time(e1) * 1e-3) / 1e6
+                     for (s0, e0), (s1, e1) in zip(bounds[:-1], bounds[1:])]
         kern_ms = [a.elapsed_time(b) for a, b in ev_pairs]
         diag = pipe.diagnostics()
         # practical ceiling: the same access pattern as a plain 27-stream copy
@@ -453,6 +462,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.storage == 0 else "f32 compute, f16 storage",
         "data": "synthetic",
+        "segments": {"mlups": [round(x, 1) for x in seg_mlups], "median_mlups": round(float(np.median(seg_mlups)), 1),
+                     "all_node_mlups": round(mlups * cfg["nx"] * cfg["ny"] / (nf / cfg["nz"]), 1)},
         "config": {"workload": f"{args.workload} pipe {cfg['nx']}x{cfg['ny']}x{cfg['nz']} R={cfg['radius']}",
                    "fluid_nodes": nf, "batch": cfg["batch"], "storage": "fp32" if args.storage == 0 else "fp16",
                    "tau": round(cfg["tau"], 6), "n_modes": cfg["n_modes"], "force_off_step": cfg["force_off_step"],
