@@ -153,6 +153,25 @@ def leg_paper(steps=300, ntheta=1024, mmax=10, reps=50):
     return r
 
 
+def leg_turbulent_stats(steps=20000, stats_from=10000):
+    """The turbulent pipe's full run (20,000 steps, trigger force for the
+    first 5,000) with the u_z statistics over the second half, sampled every
+    100 steps: rms, skewness and flatness profiles (Eq. (urmsformula)), in
+    wall units, at a few radii."""
+    import numpy as np
+    from paper_2405_12082_amd import run
+    res = run.run("turbulent", steps, stats_from, every=100, progress=steps, log=lambda s: None)
+    p = res["profiles"]
+    yp = np.asarray(p["y_plus"])
+    pick = [int(np.argmin(np.abs(yp - y))) for y in (5.0, 15.0, 30.0, 60.0, 120.0)] + [0]
+    prof = {k: [round(float(np.asarray(p[k])[i]), 4) for i in pick]
+            for k in ("y_plus", "U_plus", "rms_plus", "skewness", "flatness")}
+    nf = res["fluid_nodes"]
+    return {"steps": steps, "stats_window": [stats_from, steps], "samples": res["samples"],
+            "wall_time_s": res["wall_time_s"], "mlups_whole_run": round(nf * steps / res["wall_time_s"] / 1e6, 1),
+            "profiles_at": prof}
+
+
 def leg_batched(steps=200, graph_k=50):
     """64 independent pipes 64x64x256 (R = 30) with their own seeded forcing:
     one context, autotuned launch geometry and step order, graph replay;
@@ -340,7 +359,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,aa,bouzidi,paper,batched,adjoint,precision",
+    ap.add_argument("--legs", default="fp16,aa,bouzidi,paper,batched,adjoint,precision,turbulent_stats",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -485,7 +504,7 @@ def main():
     extra = {}
     for leg in legs:
         extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "paper": leg_paper,
-                      "batched": leg_batched,
+                      "batched": leg_batched, "turbulent_stats": leg_turbulent_stats,
                       "adjoint": leg_adjoint,
                       "precision": leg_precision}[leg]()
     if extra:
