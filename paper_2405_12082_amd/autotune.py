@@ -2,8 +2,8 @@
 
 Exhaustive search over (threads per block, z planes per thread, tile order,
 pipes per launch, step order) on a live context: each candidate is set with
-``lbm_set_launch`` and timed over a few steps with HIP events on the pipe's
-stream.  The state is saved before and restored after the search, so tuning
+``lbm_set_launch`` and timed over a replay of a graph of a few steps with HIP
+events on the pipe's stream.  The state is saved before and restored after the search, so tuning
 does not advance the simulation.  Results are cached in a JSON file keyed by
 the pipe shape, batch, storage, buffer pattern and GPU architecture.
 :func:`choose_pattern` tunes the two-buffer and the AA pattern of a
@@ -28,21 +28,28 @@ def _key(pipe) -> str:
 
 
 def candidates(batch: int):
-    ppl = sorted({batch, max(1, batch // 2), max(1, batch // 4), max(1, batch // 8), 1}, reverse=True)
+    # pipes per launch: fractions of the batch, and a few small groups whose
+    # working set can stay in the 256 MB last-level cache across the steps of
+    # a pipe-major replay
+    small = {p for p in (1, 2, 3, 4, 6) if p <= batch}
+    ppl = sorted({batch, max(1, batch // 2), max(1, batch // 4), max(1, batch // 8)} | small, reverse=True)
     orders = (0, 1) if batch > 1 else (0,)
-    for block, zchunk, xcd, p, pm in itertools.product((64, 128, 256, 512), (1, 2, 4, 8, 16), (0, 1, 8), ppl, orders):
+    for block, zchunk, xcd, p, pm in itertools.product((64, 128, 256, 512), (1, 2, 4, 8), (0, 1, 8), ppl, orders):
         if pm == 1 and p == batch:
             continue  # one group: both orders are the same launch sequence
         yield dict(block=block, zchunk=zchunk, xcd_remap=xcd, pipes_per_launch=p, pipe_major=pm)
 
 
 def _time(pipe, steps: int) -> float:
+    """ms per step of graph replays of ``steps`` steps (the way ensembles are
+    run), after one replay that captures the graph."""
+    steps += steps % 2
     stream = pipe.stream
-    pipe.step(2)
+    pipe.step_graph(steps, steps)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    pipe.step(steps)
+    pipe.step_graph(steps, steps)
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / steps
