@@ -73,7 +73,7 @@ def _events(stream):
     return a, b
 
 
-def leg_fp16(steps=500, storage=1, pattern=0, wall=0, preset="turbulent"):
+def leg_fp16(steps=500, storage=1, pattern=0, wall=0, preset="turbulent", fused=None):
     """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
     import torch
     import lbm_inputs as LI
@@ -86,6 +86,8 @@ def leg_fp16(steps=500, storage=1, pattern=0, wall=0, preset="turbulent"):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         p = P.Pipe(cfg, amps, stream=stream)
+        if fused:
+            p.set_fused(*fused)
         p.step(20)
         a, b = _events(stream)
         a.record(stream)
@@ -109,6 +111,20 @@ def leg_aa(steps=500):
     place (half the state memory; same results as two buffers)."""
     r = leg_fp16(steps, storage=0, pattern=1)
     r["pattern"] = "AA (in place)"
+    return r
+
+
+def leg_two_step(steps=200, zchunk=32, xcd_remap=1):
+    """The turbulent pipe in FP32 with two time steps per launch (temporal
+    blocking: step n on a tile and its halo ring into LDS, step n+1 from
+    there; the state crosses HBM once per two steps, 108 algorithmic bytes
+    per update).  Same states as single steps, bitwise."""
+    r = leg_fp16(steps, storage=0, fused=(2, zchunk, xcd_remap))
+    r["bytes_per_update"] = 108
+    gbs = r["value"] * 1e6 * 108 / 1e9
+    r["achieved_gbs"] = round(gbs, 1)
+    r["frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    r["launch"] = {"steps_per_launch": 2, "zchunk": zchunk, "xcd_remap": xcd_remap}
     return r
 
 
@@ -359,7 +375,7 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,aa,bouzidi,paper,batched,adjoint,precision,turbulent_stats",
+    ap.add_argument("--legs", default="fp16,aa,bouzidi,two_step,paper,batched,adjoint,precision,turbulent_stats",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -504,6 +520,7 @@ def main():
     extra = {}
     for leg in legs:
         extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "paper": leg_paper,
+                      "two_step": leg_two_step,
                       "batched": leg_batched, "turbulent_stats": leg_turbulent_stats,
                       "adjoint": leg_adjoint,
                       "precision": leg_precision}[leg]()

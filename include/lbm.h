@@ -159,6 +159,23 @@ int lbm_step_persistent(lbm_ctx *ctx, int32_t n);
 int lbm_set_launch(lbm_ctx *ctx, int32_t block, int32_t zchunk, int32_t xcd_remap, int32_t pipes_per_launch,
                    int32_t pipe_major);
 
+/* Run pairs of steps of lbm_step and lbm_step_graph as one launch each
+ * (temporal blocking; steps_per_launch = 2) or one step per launch (1).  The
+ * two-step kernel cuts the cross-section into 14 x 14 column tiles; a
+ * workgroup runs step n on its tile and a ring of halo columns, keeps those
+ * post-collision values in LDS, and runs step n+1 on the tile from them one
+ * plane behind as it marches along z (zchunk output planes per workgroup,
+ * 1..1024), so the state crosses HBM once per two steps.  Each step is the
+ * arithmetic of Eqs. (collision), (streaming) and (fbc1) at Delta = 1/2,
+ * the same as one step per launch (FP16 storage rounds the intermediate
+ * state through its codec).  xcd_remap orders the two-step launch's
+ * workgroups as in lbm_config.  Needs the two-buffer pattern, the halfway
+ * bounce-back wall and FP32 or FP16 storage.  An odd step count ends with
+ * one single step.  0 (-1 for xcd_remap) keeps a setting.  Drops captured
+ * graphs.  Errors: LBM_EINVAL for values out of range or an unsupported
+ * configuration. */
+int lbm_set_fused(lbm_ctx *ctx, int32_t steps_per_launch, int32_t zchunk, int32_t xcd_remap);
+
 /* Current step index n (the state held is f^n, before its collision). */
 int lbm_get_step(const lbm_ctx *ctx, int64_t *step);
 

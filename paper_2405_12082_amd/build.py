@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_runtime.hip", "lbm_kernels.hip", "lbm_adjoint.hip", "lbm_structures.hip"]
+SOURCES = ["lbm_runtime.hip", "lbm_kernels.hip", "lbm_fused.hip", "lbm_adjoint.hip", "lbm_structures.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -475,6 +475,21 @@ __device__ __forceinline__ void body_force(const Geom &g, int z, float sig, floa
     }
 }
 
+// One node's collision at a(x, n): moments, equilibrium, forcing and the
+// relaxation, in place on the gathered deviations v.
+template <typename T>
+__device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px, float py,
+                                        float pq, int z)
+{
+    using R = typename RealOf<T>::type;
+    R ax, ay, az;
+    body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
+    const Moments<R> m = moments_of<R>(v);
+    R ux, uy, uz;
+    const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, R(g.omega), ux, uy, uz);
+    post_collision_all<R>(c, v);
+}
+
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs
 // (workgroup w runs on XCD w % 8), each with its own L2.  remap == 0:
 // dispatch order (neighbouring tiles on different XCDs); remap == 1: XCD x

@@ -34,6 +34,24 @@ struct Tiles {
     __host__ __device__ long long count() const { return (long long)nkb * nzc; }
 };
 
+// Two time steps per launch (temporal blocking): the cross-section is cut
+// into 14 x 14 column tiles; a workgroup takes one tile, its ring of halo
+// columns (a 16 x 16 box, one thread per box column) and a range of zchunk
+// planes.  box[tile][slot] is the column of each box slot (periodic wrap),
+// with FUSED_OWNED set on the tile's own interior columns, or -1 where the
+// box slot is solid.
+constexpr int FUSED_BX = 16, FUSED_BY = 16, FUSED_BOX = FUSED_BX * FUSED_BY;
+constexpr int FUSED_IN = FUSED_BX - 2;  // interior columns per tile row
+constexpr int FUSED_OWNED = 1 << 30;
+struct Tiles2 {
+    int nt;           // tiles with at least one owned fluid column
+    int zchunk, nzc;  // output planes per workgroup, z-chunks
+    int xcd;          // workgroup -> tile order, as Tiles::xcd
+    int b0, nb;       // pipes covered by the launch
+    const int *box;   // [nt][FUSED_BOX]
+    __host__ __device__ long long count() const { return (long long)nt * nzc; }
+};
+
 // Forms of a population buffer between steps:
 //  FORM_S: slot i of node y holds g*_i(y, n-1), the post-collision value that
 //          node y + c_i pulls (two-buffer pattern);
@@ -72,6 +90,10 @@ struct RingArgs {
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
+// steps n and n+1 in one launch (two-buffer pattern, bounce-back wall, FP32
+// or FP16 storage): src holds the state of step n, dst receives step n+2
+hipError_t launch_step2(int storage, const Geom &g, const Tiles2 &t, const void *src, void *dst, int step_off,
+                        hipStream_t s);
 // AA pattern, in place: odd = 0 reads FORM_N and leaves FORM_W, odd = 1 the reverse
 hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf, int odd, int step_off, hipStream_t s);
 // persistent launch: blocks = groups * per_group workgroups, group q owning

@@ -60,19 +60,6 @@ __device__ __forceinline__ void load_columns(const Geom &g, int k, int (&col)[9]
 // swapped -> FORM_W; odd n: gather FORM_W, push to the neighbours -> FORM_N).
 enum StepMode : int { STEP_AB = 0, STEP_AA_EVEN = 1, STEP_AA_ODD = 2 };
 
-template <typename T>
-__device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px, float py,
-                                        float pq, int z)
-{
-    using R = typename RealOf<T>::type;
-    R ax, ay, az;
-    body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
-    const Moments<R> m = moments_of<R>(v);
-    R ux, uy, uz;
-    const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, R(g.omega), ux, uy, uz);
-    post_collision_all<R>(c, v);
-}
-
 // One tile of one time step (column k of the tile, its z planes): gather of
 // g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
 // For the AA modes src and dst are the same buffer.

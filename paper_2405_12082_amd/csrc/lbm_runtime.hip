@@ -30,6 +30,7 @@ constexpr int kObsZChunk = 16;               // z planes per thread for observat
 #endif
 constexpr int kAdjZChunk = LBM_ADJ_ZCHUNK;   // z planes per thread for the adjoint step
 constexpr int kMaxRing = 4096;               // ring points of the coherent-structure sampling
+constexpr int kDefaultZChunk2 = 32;          // output planes per workgroup of the two-step kernel
 // default threads per block by storage (turbulent pipe, graph replays: FP32
 // 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256); the interpolated
 // wall is best at 256 threads and 2 planes (1.244 ms vs 1.281 at 512)
@@ -46,10 +47,12 @@ struct Layout {
     std::vector<int> colmap;       // [ny][nx] -> column or -1
     int ncol = 0, P = 0;
     Tiles step{}, obs{}, adj{};
+    std::vector<int> box;          // two-step kernel: [tiles][FUSED_BOX] box columns
+    int nt2 = 0;                   // its tiles
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
     // workspace offsets
-    size_t off_state[2], off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
+    size_t off_state[2], off_box, off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_grad_base, off_modes;
     size_t off_ring_nodes, off_ring_idx, off_ring_w, off_twiddle;
@@ -119,6 +122,28 @@ int build_layout(const lbm_config *cfg, Layout &L)
             }
     L.ncol = (int)L.colx.size();
     if (L.ncol == 0) return bad("the cross-section has no fluid column");
+    // tiles of the two-step kernel: 14 x 14 interiors with a halo ring
+    // (periodic wrap); tiles without an own fluid column are dropped
+    L.box.clear();
+    for (int ty = 0; ty * FUSED_IN < c.ny; ++ty)
+        for (int tx = 0; tx * FUSED_IN < c.nx; ++tx) {
+            int box[FUSED_BOX];
+            bool any = false;
+            for (int ly = 0; ly < FUSED_BY; ++ly)
+                for (int lx = 0; lx < FUSED_BX; ++lx) {
+                    const int ux = tx * FUSED_IN - 1 + lx, uy = ty * FUSED_IN - 1 + ly;
+                    const int x = (ux % c.nx + c.nx) % c.nx, y = (uy % c.ny + c.ny) % c.ny;
+                    int v = L.colmap[(size_t)y * c.nx + x];
+                    const bool interior = lx >= 1 && lx <= FUSED_IN && ly >= 1 && ly <= FUSED_IN;
+                    if (v >= 0 && interior && ux < c.nx && uy < c.ny) {
+                        v |= FUSED_OWNED;
+                        any = true;
+                    }
+                    box[ly * FUSED_BX + lx] = v;
+                }
+            if (any) L.box.insert(L.box.end(), box, box + FUSED_BOX);
+        }
+    L.nt2 = (int)(L.box.size() / FUSED_BOX);
     L.P = (int)align_up((size_t)L.ncol, 64);
     if ((long long)27 * c.nz * L.P >= (1LL << 31)) {
         std::snprintf(buf, sizeof buf, "pipe too large: 27*nz*pitch = %lld must be < 2^31",
@@ -144,6 +169,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_state[0] = take(L.state_bytes);
     L.off_state[1] = c.pattern == 1 ? L.off_state[0] : take(L.state_bytes);  // AA: one buffer
     L.off_nbr = take(9 * P * sizeof(int));
+    L.off_box = take(L.box.size() * sizeof(int));
     L.off_bcoef = c.wall == 1 ? take(9 * P * sizeof(double)) : 0;
     L.off_colxy = take(P * sizeof(unsigned));
     L.off_fshape = take(B * 3 * P * sizeof(float));
@@ -238,6 +264,11 @@ struct lbm_ctx {
     int ppl = 1;         // pipes per step launch
     int pipe_major = 0;  // 1: each pipe group runs all steps of a call before the next group
     int graph_k[2] = {0, 0};
+    // two steps per launch (fuse == 2): the two-step kernel writes step n+2
+    // into the other buffer, so the buffer of step n is (n + flip) & 1
+    int fuse = 1;
+    int flip = 0;
+    Tiles2 t2{};
     // adjoint
     bool adj_ready = false;
     long long cursor = -1, obs_begin = 0, obs_end = 0;
@@ -251,7 +282,9 @@ struct lbm_ctx {
     double ring_r0 = -1.0;
     int ring_n = 0, tw_n = 0;
 
-    void *state(long long n) const { return ws + L.off_state[n & 1]; }
+    int buf(long long n) const { return (int)((n + flip) & 1); }
+    void *state(long long n) const { return ws + L.off_state[buf(n)]; }
+    bool can_fuse() const { return cfg.pattern == 0 && cfg.wall == 0 && cfg.storage != 2; }
     // form of the buffer that holds the state of step n
     int form(long long n) const { return cfg.pattern == 1 ? ((n & 1) ? FORM_W : FORM_N) : FORM_S; }
 };
@@ -280,33 +313,62 @@ int fail(lbm_ctx *c, int code, const std::string &msg)
         if ((ctx)->sticky) return LBM_EHIP;                                                                 \
     } while (0)
 
-// n steps from step index `first` (state buffer parity) for every pipe,
-// one launch per group of pipes_per_launch pipes, step-major or pipe-major
-hipError_t launch_steps(lbm_ctx *c, long long first, int n, hipStream_t s)
+// n steps from step index `first` for every pipe, one launch per group of
+// pipes_per_launch pipes, step-major or pipe-major.  With fuse == 2, pairs
+// of steps run as one two-step launch (a single step completes an odd n).
+// flip: the buffer flip at `first` (flip_after gives the one after).
+hipError_t launch_steps(lbm_ctx *c, long long first, int n, int flip, hipStream_t s)
 {
     const int B = c->cfg.batch;
-    auto one = [&](int b0, int j) {
+    struct Unit {
+        int j, len, bi;  // first step offset, 1 or 2 steps, source buffer
+    };
+    std::vector<Unit> units;
+    for (int j = 0; j < n;) {
+        const int bi = (int)((first + j + flip) & 1);
+        if (c->fuse == 2 && j + 2 <= n) {
+            units.push_back({j, 2, bi});
+            flip ^= 1;
+            j += 2;
+        } else {
+            units.push_back({j, 1, bi});
+            j += 1;
+        }
+    }
+    auto one = [&](int b0, const Unit &u) {
+        const int nb = std::min(c->ppl, B - b0);
+        void *src = c->ws + c->L.off_state[u.bi], *dst = c->ws + c->L.off_state[u.bi ^ 1];
+        if (u.len == 2) {
+            Tiles2 t = c->t2;
+            t.b0 = b0;
+            t.nb = nb;
+            return launch_step2(c->cfg.storage, c->geom, t, src, dst, u.j, s);
+        }
         Tiles t = c->L.step;
         t.b0 = b0;
-        t.nb = std::min(c->ppl, B - b0);
+        t.nb = nb;
         if (c->cfg.pattern == 1)
-            return launch_step_aa(c->cfg.storage, c->geom, t, c->state(first + j), (int)((first + j) & 1), j, s);
-        return launch_step(c->cfg.storage, c->geom, t, c->state(first + j), c->state(first + j + 1), j, s);
+            return launch_step_aa(c->cfg.storage, c->geom, t, src, (int)((first + u.j) & 1), u.j, s);
+        return launch_step(c->cfg.storage, c->geom, t, src, dst, u.j, s);
     };
     hipError_t e = hipSuccess;
     if (c->pipe_major) {
         for (int b0 = 0; b0 < B && e == hipSuccess; b0 += c->ppl)
-            for (int j = 0; j < n && e == hipSuccess; ++j) e = one(b0, j);
+            for (size_t q = 0; q < units.size() && e == hipSuccess; ++q) e = one(b0, units[q]);
     } else {
-        for (int j = 0; j < n && e == hipSuccess; ++j)
-            for (int b0 = 0; b0 < B && e == hipSuccess; b0 += c->ppl) e = one(b0, j);
+        for (size_t q = 0; q < units.size() && e == hipSuccess; ++q)
+            for (int b0 = 0; b0 < B && e == hipSuccess; b0 += c->ppl) e = one(b0, units[q]);
     }
     return e;
 }
 
+// the buffer flip after n more steps from the current state
+int flip_after(const lbm_ctx *c, int n) { return c->flip ^ (c->fuse == 2 ? (n / 2) & 1 : 0); }
+
 int do_step_eager(lbm_ctx *c, int n)
 {
-    HIPCHK(c, launch_steps(c, c->step, n, c->stream));
+    HIPCHK(c, launch_steps(c, c->step, n, c->flip, c->stream));
+    c->flip = flip_after(c, n);
     if (n > 0) HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
     c->step += n;
     return LBM_OK;
@@ -433,6 +495,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = h2d(L.off_nbr, nbr.data(), nbr.size() * sizeof(int));
+    if (e == hipSuccess) e = h2d(L.off_box, L.box.data(), L.box.size() * sizeof(int));
     if (e == hipSuccess) e = h2d(L.off_colxy, colxy.data(), colxy.size() * sizeof(unsigned));
     if (e == hipSuccess && g.wall == 1) e = h2d(L.off_bcoef, bcoef.data(), bcoef.size() * sizeof(double));
     if (e == hipSuccess) e = h2d(L.off_fshape, fshape.data(), fshape.size() * sizeof(float));
@@ -464,6 +527,8 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     G.n_sigma = L.n_sigma;
     G.step_dev = (const long long *)(ws + L.off_step);
     G.omega = (float)(1.0 / g.tau);
+    c->t2 = Tiles2{L.nt2, kDefaultZChunk2, (g.nz + kDefaultZChunk2 - 1) / kDefaultZChunk2, 1, 0, g.batch,
+                   (const int *)(ws + L.off_box)};
     G.accel_z = (float)g.accel_z;
 
     c->step = 0;
@@ -493,34 +558,38 @@ int lbm_step_graph(lbm_ctx *c, int32_t n, int32_t k)
 {
     CHECK_CTX(c);
     if (n < 0 || k < 2 || k > 1024 || (k & 1)) return fail(c, LBM_EINVAL, "lbm_step_graph: need n >= 0, even k in 2..1024");
-    const int par = (int)(c->step & 1);
     if (n >= k) {
-        if (!c->graph[par] || c->graph_k[par] != k) {
-            if (c->graph[par]) {
-                (void)hipGraphExecDestroy(c->graph[par]);
-                c->graph[par] = nullptr;
-            }
-            hipGraph_t gr = nullptr;
-            HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = hipSuccess;
-            e = launch_steps(c, c->step, k, c->cap_stream);
-            if (e == hipSuccess) e = launch_set_step(const_cast<long long *>(c->geom.step_dev), k, 1, c->cap_stream);
-            const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
-            if (e != hipSuccess || e2 != hipSuccess) {
-                if (gr) (void)hipGraphDestroy(gr);
-                return fail(c, LBM_EHIP, std::string("graph capture failed: ") +
-                                             hipGetErrorString(e != hipSuccess ? e : e2));
-            }
-            hipGraphExec_t ex = nullptr;
-            const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(gr);
-            if (e3 != hipSuccess) return fail(c, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
-            c->graph[par] = ex;
-            c->graph_k[par] = k;
-        }
+        // one graph per starting buffer: with an odd number of two-step
+        // launches per graph, consecutive replays alternate between them
         const int reps = n / k;
-        for (int r = 0; r < reps; ++r) HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
-        c->step += (long long)reps * k;
+        for (int r = 0; r < reps; ++r) {
+            const int par = c->buf(c->step);
+            if (!c->graph[par] || c->graph_k[par] != k) {
+                if (c->graph[par]) {
+                    (void)hipGraphExecDestroy(c->graph[par]);
+                    c->graph[par] = nullptr;
+                }
+                hipGraph_t gr = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = launch_steps(c, c->step, k, c->flip, c->cap_stream);
+                if (e == hipSuccess) e = launch_set_step(const_cast<long long *>(c->geom.step_dev), k, 1, c->cap_stream);
+                const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return fail(c, LBM_EHIP, std::string("graph capture failed: ") +
+                                                 hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                hipGraphExec_t ex = nullptr;
+                const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e3 != hipSuccess) return fail(c, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+                c->graph[par] = ex;
+                c->graph_k[par] = k;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[par], c->stream));
+            c->flip = flip_after(c, k);
+            c->step += k;
+        }
         n -= reps * k;
     }
     return do_step_eager(c, n);
@@ -589,6 +658,30 @@ int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap,
     }
     if (ppl) c->ppl = ppl;
     if (pipe_major >= 0) c->pipe_major = pipe_major;
+    for (int p = 0; p < 2; ++p)
+        if (c->graph[p]) {
+            (void)hipGraphExecDestroy(c->graph[p]);
+            c->graph[p] = nullptr;
+            c->graph_k[p] = 0;
+        }
+    return LBM_OK;
+}
+
+int lbm_set_fused(lbm_ctx *c, int32_t steps_per_launch, int32_t zchunk, int32_t xcd_remap)
+{
+    CHECK_CTX(c);
+    if (steps_per_launch < 0 || steps_per_launch > 2) return fail(c, LBM_EINVAL, "steps_per_launch must be 0, 1 or 2");
+    if (steps_per_launch == 2 && !c->can_fuse())
+        return fail(c, LBM_EINVAL, "two steps per launch need the two-buffer pattern, the halfway bounce-back wall "
+                                   "and FP32 or FP16 storage");
+    if (zchunk < 0 || zchunk > 1024) return fail(c, LBM_EINVAL, "zchunk must be in 0..1024");
+    if (xcd_remap < -1 || xcd_remap > 4096) return fail(c, LBM_EINVAL, "xcd_remap must be in -1..4096");
+    if (steps_per_launch) c->fuse = steps_per_launch;
+    if (zchunk) {
+        c->t2.zchunk = zchunk;
+        c->t2.nzc = (c->cfg.nz + zchunk - 1) / zchunk;
+    }
+    if (xcd_remap >= 0) c->t2.xcd = xcd_remap;
     for (int p = 0; p < 2; ++p)
         if (c->graph[p]) {
             (void)hipGraphExecDestroy(c->graph[p]);

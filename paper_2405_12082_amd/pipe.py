@@ -92,6 +92,12 @@ class Pipe:
         self._check(self.lib.lbm_set_launch(self._ctx, int(block), int(zchunk), int(xcd_remap),
                                             int(pipes_per_launch), int(pipe_major)), "lbm_set_launch")
 
+    def set_fused(self, steps_per_launch: int = 0, zchunk: int = 0, xcd_remap: int = -1):
+        """Two steps per launch (2) or one (1) for step / step_graph; zchunk:
+        output planes per workgroup of the two-step kernel; 0 / -1 keep."""
+        self._check(self.lib.lbm_set_fused(self._ctx, int(steps_per_launch), int(zchunk), int(xcd_remap)),
+                    "lbm_set_fused")
+
     def step_persistent(self, n: int):
         """n steps in one persistent cooperative launch (synchronises)."""
         self._check(self.lib.lbm_step_persistent(self._ctx, int(n)), "lbm_step_persistent")
