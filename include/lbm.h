@@ -103,6 +103,8 @@ typedef struct {
     int64_t state_bytes;     /* bytes of one population state (all pipes) */
     int64_t workspace_bytes; /* bytes lbm_init needs */
     int64_t bytes_per_update;/* algorithmic HBM bytes per fluid-node update of lbm_step */
+    int64_t population_stride; /* elements between the populations of one pipe: nz * plane_pitch,
+                                  padded by 2368 when that is a multiple of 4096 */
 } lbm_layout;
 
 /* Check a configuration and report its layout.  Host only.

@@ -36,6 +36,7 @@ class LbmLayout(C.Structure):
     _fields_ = [
         ("n_fluid_columns", C.c_int64), ("plane_pitch", C.c_int64), ("n_fluid_nodes", C.c_int64),
         ("state_bytes", C.c_int64), ("workspace_bytes", C.c_int64), ("bytes_per_update", C.c_int64),
+        ("population_stride", C.c_int64),
     ]
 
 

@@ -12,8 +12,8 @@ struct Geom {
     int ncol;        // fluid columns of one cross-section
     int P;           // plane pitch (elements), multiple of 64
     int nx, ny, nz, B;
-    int pstride;     // nz * P: elements between populations of one pipe
-    long long pipe;  // 27 * nz * P: elements between pipes
+    int pstride;     // elements between populations of one pipe (nz * P, padded)
+    long long pipe;  // 27 * pstride: elements between pipes
     const int *nbr;          // [9][P]: column of (x+dx, y+dy), -1 if solid
     const unsigned *colxy;   // [P]: x | y << 16
     const float *fshape;     // [B][3][P]: trigger shape sums (P_x, P_y, Q)

@@ -370,10 +370,11 @@ def test_recompute_records_the_stepped_states(gpu):
     p.recompute(start, s0, ring)
     torch.cuda.synchronize()
     ncol, P = int(p.layout.n_fluid_columns), int(p.layout.plane_pitch)
-    n = 27 * cfg["nz"] * P
+    ps, nz = int(p.layout.population_stride), cfg["nz"]
 
     def valid(blob):  # the stored columns of every (population, plane); padding excluded
-        return blob[:4 * n].view(torch.float32).reshape(27 * cfg["nz"], P)[:, :ncol]
+        pops = blob[:4 * 27 * ps].view(torch.float32).reshape(27, ps)[:, :nz * P]
+        return pops.reshape(27 * nz, P)[:, :ncol]
 
     for j in range(5):
         assert torch.equal(valid(ring[j]), valid(ref[j])), j

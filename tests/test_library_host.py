@@ -34,8 +34,11 @@ def test_layout_counts_fluid_columns(name, ncol, nodes, oracle_mod):
     assert lay.n_fluid_nodes == nodes
     assert lay.plane_pitch % 64 == 0 and lay.plane_pitch >= ncol
     assert lay.bytes_per_update == 216
-    elems = 27 * cfg["nz"] * lay.plane_pitch * cfg["batch"]
-    assert lay.state_bytes >= 4 * elems
+    ps = lay.population_stride
+    assert ps % 64 == 0 and ps >= cfg["nz"] * lay.plane_pitch
+    assert ps % 4096 != 0  # streams of a step not aligned modulo 16 KiB (FP32)
+    assert ps - cfg["nz"] * lay.plane_pitch in (0, 2368)
+    assert lay.state_bytes >= 4 * 27 * ps * cfg["batch"]
     if name == "laminar":
         # same fluid set as the oracle's mask
         o = oracle_mod.Pipe(oracle_mod.make_config(**cfg))
