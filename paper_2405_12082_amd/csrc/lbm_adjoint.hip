@@ -246,26 +246,33 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     gp[2] = G[2];
 }
 
-// acc[b][k] += sigma(n) * (sum over the z-chunks of step n's column partials),
-// fixed order: the force sensitivity of every column, summed over the steps
-// of the sweep so far
-__global__ __launch_bounds__(256) void k_grad_accumulate(const double *__restrict__ part, double *__restrict__ acc,
-                                                         int nzc, int P, int ncol, int B, double sigma)
+// acc[b][k] += sigma(n) * (sum over the z-chunks of step n's column partials):
+// the force sensitivity of every column, summed over the steps of the sweep
+// so far.  The partials of one (pipe, z-chunk) are 3 P consecutive doubles;
+// a block takes 64 of them (one per lane), its 16 waves sum every 16th
+// z-chunk each, and wave 0 adds the 16 wave sums in a fixed order
+// (deterministic).
+constexpr int kAccWaves = 16;
+__global__ __launch_bounds__(64 * kAccWaves) void k_grad_accumulate(const double *__restrict__ part,
+                                                                    double *__restrict__ acc, int nzc, int P,
+                                                                    int ncol, int blocks_per_pipe, double sigma)
 {
-    const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (long long)B * ncol) return;
-    const int b = (int)(idx / ncol), k = (int)(idx % ncol);
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int zc = 0; zc < nzc; ++zc) {
-        const double *p = part + (((size_t)b * nzc + zc) * P + k) * 3;
-        s[0] += p[0];
-        s[1] += p[1];
-        s[2] += p[2];
+    __shared__ double red[kAccWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = blockIdx.x / blocks_per_pipe;
+    const int e = (blockIdx.x % blocks_per_pipe) * 64 + lane;  // 3 k + component
+    const bool in = e < 3 * ncol;
+    double s = 0.0;
+    if (in)
+        for (int zc = w; zc < nzc; zc += kAccWaves) s += part[((size_t)b * nzc + zc) * 3 * P + e];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && in) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kAccWaves; ++q) t += red[q][lane];
+        acc[(size_t)b * 3 * P + e] += sigma * t;
     }
-    double *o = acc + ((size_t)b * P + k) * 3;
-    o[0] += sigma * s[0];
-    o[1] += sigma * s[1];
-    o[2] += sigma * s[2];
 }
 
 // grad[b][q] = base[b][q] + sum_k acc[b][k] . shape_q(k), one block per (b, q)
@@ -315,9 +322,9 @@ hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles
 hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
                                   hipStream_t s)
 {
-    const long long n = (long long)g.B * g.ncol;
-    hipLaunchKernelGGL(k_grad_accumulate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, grad_part, acc, t.nzc,
-                       g.P, g.ncol, g.B, sigma);
+    const int per_pipe = (3 * g.ncol + 63) / 64;
+    hipLaunchKernelGGL(k_grad_accumulate, dim3((unsigned)(per_pipe * g.B)), dim3(64 * kAccWaves), 0, s, grad_part, acc,
+                       t.nzc, g.P, g.ncol, per_pipe, sigma);
     return hipGetLastError();
 }
 
