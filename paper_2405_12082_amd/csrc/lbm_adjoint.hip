@@ -58,26 +58,6 @@ __device__ __forceinline__ void gather_transpose(const R *__restrict__ lam, int 
     if constexpr (J + 1 < 27) gather_transpose<R, WALL, J + 1>(lam, pstride, P, col, k, z, zm, zp, bcoef, mu);
 }
 
-// The same transpose with the bounce-back wall, addressed like the forward
-// pull (uniform base per population, one 32-bit offset per load): q views
-// lambda^{c+1} with the in-plane neighbour columns of this column (own
-// column where solid); mu_J reads slot J of column y + c_J, and a lane whose
-// y + c_J is solid reads slot opp(J) of its own node instead.
-template <typename R, int J = 0>
-__device__ __forceinline__ void gather_transpose_bb(const Pull<R> &q, unsigned zo, unsigned zmo, unsigned zpo,
-                                                    R (&mu)[27])
-{
-    constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
-    constexpr int d = NSLOT(cx, cy);
-    const unsigned zs = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
-    R v = Codec<R>::template ld<J>(q.base + J * q.pbytes, zs + q.colo[d]);
-    if constexpr (d != 4) {
-        if (q.wall & (1u << d)) v = Codec<R>::template ld<J>(q.base + OPP(J) * q.pbytes, zo + q.own);
-    }
-    mu[J] = v;
-    if constexpr (J + 1 < 27) gather_transpose_bb<R, J + 1>(q, zo, zmo, zpo, mu);
-}
-
 // per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
 // forward collision): d_0 = -3u^2/2, d_+-1 = +-3u + 3u^2; d' and d'' below
 template <typename R> struct AxisR {
@@ -145,18 +125,16 @@ __device__ __forceinline__ void dual_dots(const R (&mu)[27], R (&D)[5])
     if constexpr (I + 1 < 27) dual_dots<R, I + 1>(mu, D);
 }
 
-// lambda^c_J = sum_q M_q(c_J) <df*/dq, mu> at this node: slot J at byte
-// offset off of population J (base + J * pbytes)
 template <typename R, int J = 0>
-__device__ __forceinline__ void write_lambda(char *base, size_t pbytes, unsigned off, R Ldr, R Ljx, R Ljy, R Ljz,
+__device__ __forceinline__ void write_lambda(R *__restrict__ lam, int pstride, size_t off, R Ldr, R Ljx, R Ljy, R Ljz,
                                              const R (&Dp)[5])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
     R v = Ldr + R(cx) * Ljx + R(cy) * Ljy + R(cz) * Ljz;
     v += R(cx * cy) * Dp[0] + R(cx * cz) * Dp[1] + R(cy * cz) * Dp[2];
     v += R(cx * cx - cy * cy) * Dp[3] + R(cx * cx - cz * cz) * Dp[4];
-    Codec<R>::template st<J>(base + J * pbytes, off, v);
-    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(base, pbytes, off, Ldr, Ljx, Ljy, Ljz, Dp);
+    lam[(size_t)J * pstride + off] = v;
+    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(lam, pstride, off, Ldr, Ljx, Ljy, Ljz, Dp);
 }
 
 #ifndef LBM_ADJ_WAVES_PER_EU
@@ -176,19 +154,15 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     const int k = kb * BLOCK + threadIdx.x;
     if (k >= g.ncol) return;
     int col[9];
-    if constexpr (WALL) {
 #pragma unroll
-        for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
-    }
+    for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
     const Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const float *fs = g.fshape + (size_t)b * 3 * g.P;
     const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
     const float sig = (a.cursor >= 0 && a.cursor < g.n_sigma) ? g.sigma[a.cursor] : 0.f;
     const R *lin = (const R *)a.lam_in + (size_t)b * g.pipe;
-    char *lout = reinterpret_cast<char *>((R *)a.lam_out + (size_t)b * g.pipe);
-    const unsigned rowr = (unsigned)g.P * sizeof(R);
-    const size_t pbr = (size_t)g.pstride * sizeof(R);
+    R *lout = (R *)a.lam_out + (size_t)b * g.pipe;
     const R om1 = R(1) - R(g.omega);
     const R we = R(a.energy_weight);
     double G[3] = {0.0, 0.0, 0.0};
@@ -226,12 +200,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
         R mu[27];
         if (a.has_next) {
-            if constexpr (WALL) {
-                gather_transpose<R, WALL>(lin, g.pstride, g.P, col, k, z, zm, zp, g.bcoef, mu);
-            } else {
-                const Pull<R> q = make_pull<R>(lin, (size_t)g.pstride, g.nbr, g.P, k);
-                gather_transpose_bb<R>(q, (unsigned)z * rowr, (unsigned)zm * rowr, (unsigned)zp * rowr, mu);
-            }
+            gather_transpose<R, WALL>(lin, g.pstride, g.P, col, k, z, zm, zp, g.bcoef, mu);
         } else {
 #pragma unroll
             for (int i = 0; i < 27; ++i) mu[i] = R(0);
@@ -266,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const R sx = h * rho * s.Sax + Qax + h * Lux;
         const R sy = h * rho * s.Say + Qay + h * Luy;
         const R sz_ = h * rho * s.Saz + Qaz + h * Luz;
-        write_lambda<R>(lout, pbr, (unsigned)z * rowr + (unsigned)k * sizeof(R), Ldr, Ljx, Ljy, Ljz, Dp);
+        write_lambda<R>(lout, g.pstride, (size_t)z * g.P + k, Ldr, Ljx, Ljy, Ljz, Dp);
         G[0] += (double)cz * (double)sx;
         G[1] += (double)cz * (double)sy;
         G[2] += (double)sz * (double)sz_;
