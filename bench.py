@@ -220,6 +220,14 @@ def leg_batched(steps=200, graph_k=50):
         b.record(stream)
         b.synchronize()
         ms_persistent = a.elapsed_time(b) / steps
+        # replays of a graph holding one persistent launch of graph_k steps
+        p.step_persistent_graph(2 * graph_k, graph_k)  # capture + warm
+        a, b = _events(stream)
+        a.record(stream)
+        p.step_persistent_graph(steps, graph_k)
+        b.record(stream)
+        b.synchronize()
+        ms_pgraph = a.elapsed_time(b) / steps
         nf = p.n_fluid
         ok = bool((p.diagnostics()[:, 4] == 0).all())
         del p
@@ -248,6 +256,8 @@ def leg_batched(steps=200, graph_k=50):
             "speedup_vs_sequential": round(ms_seq / ms_batched, 3),
             "persistent_launch": {"value": round(B * nf / (ms_persistent * 1e-3) / 1e6, 1),
                                   "ms_per_step": round(ms_persistent, 4)},
+            "persistent_launch_graph": {"value": round(B * nf / (ms_pgraph * 1e-3) / 1e6, 1),
+                                        "ms_per_step": round(ms_pgraph, 4), "steps_per_launch": graph_k},
             "state_finite": ok}
 
 

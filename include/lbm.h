@@ -148,6 +148,17 @@ int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
  * invalid.  Synchronises the stream. */
 int lbm_step_persistent(lbm_ctx *ctx, int32_t n);
 
+/* n steps as replays of a HIP graph holding ONE persistent launch of k steps
+ * (the launch of lbm_step_persistent, with the reset of its group counters
+ * and the step counter update), k even (2..2^20); one graph per starting
+ * buffer is captured on first use and kept until the launch geometry
+ * changes.  n mod k remaining steps run as lbm_step_persistent.  Same
+ * results as lbm_step (bitwise).  The barrier timeout flag is cleared once
+ * before the replays and read once after them: LBM_ESTATE if any barrier
+ * timed out (the state is then invalid).  Synchronises the stream.
+ * Errors: LBM_EINVAL for n < 0 or a bad k, LBM_EHIP if capture fails. */
+int lbm_step_persistent_graph(lbm_ctx *ctx, int32_t n, int32_t k);
+
 /* Change the launch geometry of lbm_step and lbm_step_graph on a live
  * context: threads per block (64, 128, 256, 512), z planes per thread (1..64),
  * tile order (xcd_remap 0..4096, as in lbm_config), pipes per launch (1..batch) and step order

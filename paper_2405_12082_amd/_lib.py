@@ -81,6 +81,7 @@ def lib():
         "lbm_step_persistent": ([vp, i32], C.c_int),
         "lbm_set_launch": ([vp, i32, i32, i32, i32, i32], C.c_int),
         "lbm_set_fused": ([vp, i32, i32, i32], C.c_int),
+        "lbm_step_persistent_graph": ([vp, i32, i32], C.c_int),
         "lbm_get_step": ([vp, C.POINTER(i64)], C.c_int),
         "lbm_moments": ([vp, fp, fp], C.c_int),
         "lbm_populations": ([vp, fp], C.c_int),

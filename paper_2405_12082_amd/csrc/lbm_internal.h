@@ -97,11 +97,12 @@ hipError_t launch_step2(int storage, const Geom &g, const Tiles2 &t, const void 
 // AA pattern, in place: odd = 0 reads FORM_N and leaves FORM_W, odd = 1 the reverse
 hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf, int odd, int step_off, hipStream_t s);
 // persistent launch: blocks = groups * per_group workgroups, group q owning
-// pipes [q * pipes_per_group, ...); bar: 32 words per group + 32 (error
-// flag).  aa: in place in b0, par = parity of the first step.
+// pipes [q * pipes_per_group, ...); bar: 32 words (error flag) + 32 per
+// group.  aa: in place in b0, par = parity of the first step.  cooperative:
+// hipLaunchCooperativeKernel; 0: a plain launch (for graph capture).
 hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
                                   int nsteps, unsigned *bar, int blocks, int per_group, int pipes_per_group,
-                                  hipStream_t s);
+                                  int cooperative, hipStream_t s);
 int persistent_blocks_per_cu(int storage, int aa, int wall, int block);
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
 hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,

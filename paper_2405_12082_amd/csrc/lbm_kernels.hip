@@ -621,7 +621,7 @@ hipError_t launch_step_aa(int storage, const Geom &g, const Tiles &t, void *buf,
 
 template <typename T, int BLOCK, bool AA, bool WALL>
 static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
-                               int blocks, int per_group, int ppg, hipStream_t s)
+                               int blocks, int per_group, int ppg, int coop, hipStream_t s)
 {
     Geom gg = g;
     Tiles tt = t;
@@ -629,39 +629,40 @@ static hipError_t persistent_t(const Geom &g, const Tiles &t, void *b0, void *b1
     void *args[] = {&gg, &tt, &p0, &p1, &par, &nsteps, &bar, &per_group, &ppg};
     void (*fn)(const Geom, const Tiles, T *, T *, int, int, unsigned *, int, int) =
         &k_step_persistent<T, BLOCK, AA, WALL>;
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
+    if (coop) return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(blocks), dim3(BLOCK), args, 0, s);
 }
 
 template <typename T, bool AA, bool WALL>
 static hipError_t persistent_block(const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps, unsigned *bar,
-                                   int blocks, int per_group, int ppg, hipStream_t s)
+                                   int blocks, int per_group, int ppg, int coop, hipStream_t s)
 {
     switch (t.block) {
-    case 64: return persistent_t<T, 64, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    case 128: return persistent_t<T, 128, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    case 512: return persistent_t<T, 512, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    default: return persistent_t<T, 256, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    case 64: return persistent_t<T, 64, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
+    case 128: return persistent_t<T, 128, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
+    case 512: return persistent_t<T, 512, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
+    default: return persistent_t<T, 256, AA, WALL>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
     }
 }
 // kinds: two buffers + bounce-back, AA + bounce-back, two buffers + interpolated wall
 template <typename T>
 static hipError_t persistent_pattern(int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par, int nsteps,
-                                     unsigned *bar, int blocks, int per_group, int ppg, hipStream_t s)
+                                     unsigned *bar, int blocks, int per_group, int ppg, int coop, hipStream_t s)
 {
-    if (aa) return persistent_block<T, true, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    if (g.bcoef) return persistent_block<T, false, true>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
-    return persistent_block<T, false, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, s);
+    if (aa) return persistent_block<T, true, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
+    if (g.bcoef) return persistent_block<T, false, true>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
+    return persistent_block<T, false, false>(g, t, b0, b1, par, nsteps, bar, blocks, per_group, ppg, coop, s);
 }
 
 hipError_t launch_step_persistent(int storage, int aa, const Geom &g, const Tiles &t, void *b0, void *b1, int par,
                                   int nsteps, unsigned *bar, int blocks, int per_group, int pipes_per_group,
-                                  hipStream_t s)
+                                  int coop, hipStream_t s)
 {
     if (storage == 2)
-        return persistent_pattern<double>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+        return persistent_pattern<double>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, coop, s);
     if (storage == 1)
-        return persistent_pattern<__half>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
-    return persistent_pattern<float>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, s);
+        return persistent_pattern<__half>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, coop, s);
+    return persistent_pattern<float>(aa, g, t, b0, b1, par, nsteps, bar, blocks, per_group, pipes_per_group, coop, s);
 }
 
 template <typename T, int BLOCK, bool AA, bool WALL> static int occ_t()

@@ -270,6 +270,8 @@ struct lbm_ctx {
     int ppl = 1;         // pipes per step launch
     int pipe_major = 0;  // 1: each pipe group runs all steps of a call before the next group
     int graph_k[2] = {0, 0};
+    hipGraphExec_t pgraph[2] = {nullptr, nullptr};  // persistent launches, per starting buffer
+    int pgraph_k[2] = {0, 0};
     // two steps per launch (fuse == 2): the two-step kernel writes step n+2
     // into the other buffer, so the buffer of step n is (n + flip) & 1
     int fuse = 1;
@@ -384,6 +386,67 @@ int observe(lbm_ctx *c, const ObserveArgs &o)
 {
     HIPCHK(c, launch_observe(c->cfg.storage, c->form(c->step), c->geom, c->L.obs, c->state(c->step), o, 0, c->stream));
     return LBM_OK;
+}
+
+// workgroups of a persistent launch: groups of co-resident workgroups that
+// own whole pipes, as many groups as pipes while the co-resident workgroups
+// suffice, else several pipes per group
+struct PersistentPlan {
+    int blocks, per_group, ppg, groups;
+};
+int persistent_plan(lbm_ctx *c, PersistentPlan &pl)
+{
+    int dev = 0, cus = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int aa = c->cfg.pattern == 1;
+    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, aa, c->cfg.wall, c->L.step.block);
+    if (per_cu < 1 || cus < 1) return fail(c, LBM_EHIP, "persistent launch: occupancy query failed");
+    const long long slots = (long long)per_cu * cus, per_pipe = c->L.step.count();
+    const int B = c->cfg.batch;
+    if (per_pipe * B > INT_MAX) return fail(c, LBM_EINVAL, "persistent launch: too many tiles for one launch");
+    pl.ppg = (int)((B + slots - 1) / slots);
+    pl.groups = (B + pl.ppg - 1) / pl.ppg;
+    pl.per_group = (int)std::min<long long>(slots / pl.groups, per_pipe * pl.ppg);
+    pl.blocks = pl.groups * pl.per_group;
+    return LBM_OK;
+}
+// n steps from the current state as one persistent launch plus the step
+// counter update (cooperative: a launch of its own; 0: a plain launch, for
+// graph capture, where the grid is still sized to the co-resident
+// workgroups and the barrier wait stays bounded)
+hipError_t launch_persistent(lbm_ctx *c, const PersistentPlan &pl, int n, int cooperative, hipStream_t s)
+{
+    Tiles t = c->L.step;
+    t.b0 = 0;
+    t.nb = c->cfg.batch;
+    const int aa = c->cfg.pattern == 1;
+    unsigned *bar = (unsigned *)(c->ws + c->L.off_bar);
+    hipError_t e = launch_step_persistent(c->cfg.storage, aa, c->geom, t, c->state(c->step), c->state(c->step + 1),
+                                          aa ? (int)(c->step & 1) : 0, n, bar, pl.blocks, pl.per_group, pl.ppg,
+                                          cooperative, s);
+    if (e == hipSuccess) e = launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, s);
+    return e;
+}
+// reads the persistent launches' error flag (synchronises the stream)
+int persistent_check(lbm_ctx *c, const char *what)
+{
+    unsigned err = 0;
+    HIPCHK(c, hipMemcpyAsync(&err, c->ws + c->L.off_bar, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (err) return fail(c, LBM_ESTATE, std::string(what) + ": a group barrier timed out (state invalid)");
+    return LBM_OK;
+}
+
+// captured graphs hold the launch geometry: drop them when it changes
+void drop_graphs(lbm_ctx *c)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
+        if (c->pgraph[p]) (void)hipGraphExecDestroy(c->pgraph[p]);
+        c->graph[p] = c->pgraph[p] = nullptr;
+        c->graph_k[p] = c->pgraph_k[p] = 0;
+    }
 }
 
 }  // namespace
@@ -607,36 +670,61 @@ int lbm_step_persistent(lbm_ctx *c, int32_t n)
     CHECK_CTX(c);
     if (n < 0) return fail(c, LBM_EINVAL, "lbm_step_persistent: n must be >= 0");
     if (n == 0) return LBM_OK;
-    int dev = 0, cus = 0;
-    HIPCHK(c, hipGetDevice(&dev));
-    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int aa = c->cfg.pattern == 1;
-    const int per_cu = persistent_blocks_per_cu(c->cfg.storage, aa, c->cfg.wall, c->L.step.block);
-    if (per_cu < 1 || cus < 1) return fail(c, LBM_EHIP, "lbm_step_persistent: occupancy query failed");
-    Tiles t = c->L.step;
-    t.b0 = 0;
-    t.nb = c->cfg.batch;
-    // groups of workgroups own whole pipes: as many groups as pipes while the
-    // co-resident workgroups suffice, else several pipes per group
-    const long long slots = (long long)per_cu * cus, per_pipe = t.count();
-    const int B = c->cfg.batch;
-    if (per_pipe * B > INT_MAX) return fail(c, LBM_EINVAL, "lbm_step_persistent: too many tiles for one launch");
-    const int ppg = (int)((B + slots - 1) / slots);
-    const int groups = (B + ppg - 1) / ppg;
-    const int per_group = (int)std::min<long long>(slots / groups, per_pipe * ppg);
-    const int blocks = groups * per_group;
+    PersistentPlan pl;
+    int rc = persistent_plan(c, pl);
+    if (rc != LBM_OK) return rc;
     unsigned *bar = (unsigned *)(c->ws + c->L.off_bar);
-    HIPCHK(c, launch_fill(bar, 32 * sizeof(unsigned) * ((size_t)groups + 1), c->stream));
-    HIPCHK(c, launch_step_persistent(c->cfg.storage, aa, c->geom, t, c->state(c->step), c->state(c->step + 1),
-                                     aa ? (int)(c->step & 1) : 0, n, bar,
-                                     blocks, per_group, ppg, c->stream));
-    HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
+    HIPCHK(c, launch_fill(bar, 32 * sizeof(unsigned) * ((size_t)pl.groups + 1), c->stream));
+    HIPCHK(c, launch_persistent(c, pl, n, 1, c->stream));
     c->step += n;
-    unsigned err = 0;
-    HIPCHK(c, hipMemcpyAsync(&err, bar, sizeof(err), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (err) return fail(c, LBM_ESTATE, "lbm_step_persistent: a group barrier timed out (state invalid)");
-    return LBM_OK;
+    return persistent_check(c, "lbm_step_persistent");
+}
+
+int lbm_step_persistent_graph(lbm_ctx *c, int32_t n, int32_t k)
+{
+    CHECK_CTX(c);
+    if (n < 0 || k < 2 || k > (1 << 20) || (k & 1))
+        return fail(c, LBM_EINVAL, "lbm_step_persistent_graph: need n >= 0, even k in 2..2^20");
+    PersistentPlan pl;
+    int rc = persistent_plan(c, pl);
+    if (rc != LBM_OK) return rc;
+    unsigned *bar = (unsigned *)(c->ws + c->L.off_bar);
+    const int reps = n / k;
+    if (reps > 0) {
+        HIPCHK(c, launch_fill(bar, 32 * sizeof(unsigned), c->stream));  // the error flag, once for all replays
+        for (int r = 0; r < reps; ++r) {
+            const int par = c->buf(c->step);  // k is even: a replay ends in the buffer it starts from
+            if (!c->pgraph[par] || c->pgraph_k[par] != k) {
+                if (c->pgraph[par]) {
+                    (void)hipGraphExecDestroy(c->pgraph[par]);
+                    c->pgraph[par] = nullptr;
+                }
+                hipGraph_t gr = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                // group counters and barriers (the error flag stays), one
+                // persistent launch of k steps, the step counter
+                hipError_t e = launch_fill(bar + 32, 32 * sizeof(unsigned) * (size_t)pl.groups, c->cap_stream);
+                if (e == hipSuccess) e = launch_persistent(c, pl, k, 0, c->cap_stream);
+                const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &gr);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return fail(c, LBM_EHIP, std::string("persistent graph capture failed: ") +
+                                                 hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                hipGraphExec_t ex = nullptr;
+                const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e3 != hipSuccess) return fail(c, LBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+                c->pgraph[par] = ex;
+                c->pgraph_k[par] = k;
+            }
+            HIPCHK(c, hipGraphLaunch(c->pgraph[par], c->stream));
+            c->step += k;
+        }
+        rc = persistent_check(c, "lbm_step_persistent_graph");
+        if (rc != LBM_OK) return rc;
+    }
+    return n % k ? lbm_step_persistent(c, n % k) : LBM_OK;
 }
 
 int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap, int32_t ppl, int32_t pipe_major)
@@ -665,12 +753,7 @@ int lbm_set_launch(lbm_ctx *c, int32_t block, int32_t zchunk, int32_t xcd_remap,
     }
     if (ppl) c->ppl = ppl;
     if (pipe_major >= 0) c->pipe_major = pipe_major;
-    for (int p = 0; p < 2; ++p)
-        if (c->graph[p]) {
-            (void)hipGraphExecDestroy(c->graph[p]);
-            c->graph[p] = nullptr;
-            c->graph_k[p] = 0;
-        }
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -689,12 +772,7 @@ int lbm_set_fused(lbm_ctx *c, int32_t steps_per_launch, int32_t zchunk, int32_t 
         c->t2.nzc = (c->cfg.nz + zchunk - 1) / zchunk;
     }
     if (xcd_remap >= 0) c->t2.xcd = xcd_remap;
-    for (int p = 0; p < 2; ++p)
-        if (c->graph[p]) {
-            (void)hipGraphExecDestroy(c->graph[p]);
-            c->graph[p] = nullptr;
-            c->graph_k[p] = 0;
-        }
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -1032,8 +1110,7 @@ void lbm_destroy(lbm_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    for (int p = 0; p < 2; ++p)
-        if (c->graph[p]) (void)hipGraphExecDestroy(c->graph[p]);
+    drop_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }

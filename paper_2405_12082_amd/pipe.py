@@ -102,6 +102,10 @@ class Pipe:
         """n steps in one persistent cooperative launch (synchronises)."""
         self._check(self.lib.lbm_step_persistent(self._ctx, int(n)), "lbm_step_persistent")
 
+    def step_persistent_graph(self, n: int, k: int = 50):
+        """n steps as replays of a graph holding one persistent launch of k steps."""
+        self._check(self.lib.lbm_step_persistent_graph(self._ctx, int(n), int(k)), "lbm_step_persistent_graph")
+
     def stream_copy(self, n: int = 1):
         """n copies of the state with the step's launch geometry (bandwidth ceiling)."""
         self._check(self.lib.lbm_stream_copy(self._ctx, int(n)), "lbm_stream_copy")

@@ -103,6 +103,31 @@ def test_persistent_launch_equals_eager(P, block, zchunk):
         assert np.array_equal(p.populations().cpu().numpy(), ref.populations().cpu().numpy()), n
 
 
+@pytest.mark.parametrize("pattern,wall,k", [(0, 0, 4), (1, 0, 6), (0, 1, 4)])
+def test_persistent_graph_equals_eager(P, pattern, wall, k):
+    """Replays of a graph holding one persistent launch of k steps (three
+    pipes; two buffers, AA and the interpolated wall): the states of n
+    ordinary launches after every call, including a remainder of n mod k
+    steps, a second replay of the cached graph and a call after a change of
+    the launch geometry (which recaptures it)."""
+    cfg = dict(_cfg(batch=3), pattern=pattern, wall=wall)
+    amps = _amps(cfg)
+    ref = P.Pipe(cfg, amps)
+    p = P.Pipe(cfg, amps)
+    _log(f"persistent graph pattern={pattern} wall={wall} k={k}")
+    for n in (3, 2 * k + 2, k, 1):
+        ref.step(n)
+        p.step_persistent_graph(n, k)
+        assert p.step_index == ref.step_index
+        assert np.array_equal(p.populations().cpu().numpy(), ref.populations().cpu().numpy()), n
+    p.set_launch(block=64, zchunk=2)
+    ref.step(2 * k)
+    p.step_persistent_graph(2 * k, k)
+    assert np.array_equal(p.populations().cpu().numpy(), ref.populations().cpu().numpy())
+    with pytest.raises(P.LbmError):
+        p.step_persistent_graph(4, 3)
+
+
 def test_choose_pattern_tunes_both_patterns(P, tmp_path):
     from paper_2405_12082_amd import autotune
     cfg = _cfg(batch=2)
