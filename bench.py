@@ -47,12 +47,11 @@ def measured_traffic(workload, storage):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, amps, seconds=12.0):
-    """The FP64 oracle (as it stands) on a z-slab of the same pipe: same
-    cross-section, parameters and forcing, nz = 48."""
+def _oracle_rate(cfg, amps, nz, seconds):
+    """MLUPS of the FP64 oracle on a z-slab of nz planes of the pipe."""
     from oracle import oracle as O
     c = dict(cfg)
-    c["nz"] = 48
+    c["nz"] = nz
     p = O.Pipe(O.make_config(**c), amps)
     p.step(1)
     nf = p.n_fluid
@@ -62,9 +61,43 @@ def cpu_baseline(cfg, amps, seconds=12.0):
         p.step(2)
         steps += 2
     dt = time.perf_counter() - t0
-    return {"value": nf * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{c['nx']}x{c['ny']}x{c['nz']} slab of the same pipe (R={c['radius']}), "
-                      f"{steps} steps, {nf} fluid nodes, {dt:.1f} s"}
+    return nf * steps / dt / 1e6, steps, nf, dt, O.num_threads()
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, amps, seconds=12.0, single_seconds=4.0):
+    """The FP64 oracle (as it stands) on a z-slab of the same pipe: same
+    cross-section, parameters and forcing, nz = 48, on all host threads;
+    and on one thread (a child process with OMP_NUM_THREADS=1, nz = 4)."""
+    import subprocess
+    rate, steps, nf, dt, threads = _oracle_rate(cfg, amps, 48, seconds)
+    out = {"value": rate, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{cfg['nx']}x{cfg['ny']}x48 slab of the same pipe (R={cfg['radius']}), "
+                     f"{steps} steps, {nf} fluid nodes, {dt:.1f} s",
+           "cpu_model": _cpu_model()}
+    code = ("import json, sys; sys.path.insert(0, sys.argv[1]); import bench; "
+            "r = bench._oracle_rate(json.loads(sys.argv[2]), json.loads(sys.argv[3]), 4, float(sys.argv[4])); "
+            "print(json.dumps(r))")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code, ROOT, json.dumps(cfg),
+                              json.dumps(None if amps is None else [float(a) for a in amps]), str(single_seconds)],
+                             env=env, capture_output=True, text=True, timeout=120)
+        r1 = json.loads(res.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": r1[0], "threads": r1[4],
+                                "sample": f"{cfg['nx']}x{cfg['ny']}x4 slab, {r1[1]} steps, {r1[3]:.1f} s"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 def _events(stream):
