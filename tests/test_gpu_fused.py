@@ -206,3 +206,23 @@ def test_unsupported_configurations_rejected(P):
     for bad in (dict(steps_per_launch=3), dict(zchunk=1025), dict(xcd_remap=4097)):
         with pytest.raises(P.LbmError):
             p.set_fused(**bad)
+
+
+def test_full_size_turbulent_pipe_in_the_bench_launch(P):
+    """The turbulent pipe 192 x 192 x 1152 (R = 90, log-law start, trigger
+    force) in the launch the bench times (two steps per launch, 32 planes per
+    workgroup, XCD eighths): after 2, 4 and 5 steps the state equals single
+    steps bitwise (compared on the device)."""
+    cfg = LI.preset("turbulent")
+    amps = LI.preset_amplitudes(cfg)
+    one = P.Pipe(cfg, amps)
+    two = P.Pipe(cfg, amps)
+    two.set_fused(2, 32, 1)
+    for n in (2, 2, 1):
+        one.step(n)
+        two.step(n)
+        a, _ = one.save()
+        b, _ = two.save()
+        assert torch.equal(a, b), f"step {one.step_index}"
+        del a, b
+    _log(f"full-size turbulent pipe: two-step launches == single steps over {one.step_index} steps")
