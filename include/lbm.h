@@ -73,8 +73,10 @@ typedef struct {
     double period;        /* forcing period T in steps: time factor sin(2 pi n / T) */
     int64_t force_off_step; /* trigger force applied for steps n < force_off_step */
     int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations scaled by
-                             2^k ~ 1/w_i, FP32 collision; 2: FP64 deviations and collision
-                             (reference precision, for verification) */
+                             2^k ~ 1/w_i (4, 16, 64, 256 for |c_i|^2 = 0, 1, 2, 3; stored as
+                             fp16_rne(g_i 2^k), read as fp16 value / 2^k), FP32 collision;
+                             2: FP64 deviations and collision (reference precision, for
+                             verification) */
     int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1));
                              1: interpolated wall of Eqs. (fbc1)/(fbc2) with the exact
                              fraction Delta of each cut link at r = R (two-buffer

@@ -1,8 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration bench.py
 times (needs an MI355X).
 
-* The turbulent pipe 192x192x1152 (R = 90) and the paper's pipe 300x300x600
-  (R = 149.5, interpolated wall): one fused step from seeded random
+* The turbulent pipe 192x192x1152 (R = 90; FP32, FP16 storage, AA
+  pattern) and the paper's pipe 300x300x600 (R = 149.5, interpolated
+  wall): one fused step from seeded random
   deviations with the trigger force active; every population of ~400
   sampled nodes (wall-adjacent columns, both periodic z ends, the last
   columns of the layout, random interior nodes) against the FP64 oracle's
@@ -39,14 +40,28 @@ def _log(msg):
 SEED, AMP = 2024, 0.02
 
 
-def _sampled_step_parity(P, O, name, s):
+# FP16 storage codec (include/lbm.h): g stored as fp16_rne(g 2^k), 2^k by shell
+FP16_SCALE = np.array([4.0 if s == 0 else 16.0 if s == 1 else 64.0 if s == 2 else 256.0
+                       for s in (0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3)])
+
+
+def _fp16_stored(g):
+    """What FP16 storage holds and returns for FP32 deviations g [..., 27]."""
+    g = np.asarray(g, np.float32)
+    return (np.float16(g * FP16_SCALE.astype(np.float32)).astype(np.float64) / FP16_SCALE)
+
+
+def _sampled_step_parity(P, O, name, s, **over):
     """One fused step of preset ``name`` from seeded random deviations at step
     s, in the default launch geometry (as bench.py); ~400 sampled nodes (wall
     columns, both periodic z ends, the last columns of the layout, random
     interior nodes), every population against the FP64 oracle's collide +
     stream computed node by node (halfway bounce-back or, wall = 1, the
-    interpolation of Eqs. (fbc1)/(fbc2) with the oracle's wall fraction)."""
-    cfg = LI.preset(name)
+    interpolation of Eqs. (fbc1)/(fbc2) with the oracle's wall fraction).
+    ``over`` overrides config fields (storage, pattern).  FP16 storage: the
+    oracle starts from the FP16-stored inputs, and the tolerance adds one
+    FP16 rounding of each output."""
+    cfg = dict(LI.preset(name), **over)
     amps = LI.preset_amplitudes(cfg)
     nx, ny, nz = LI.dims_of(cfg)
     ocfg = O.make_config(**cfg)
@@ -90,9 +105,12 @@ def _sampled_step_parity(P, O, name, s):
     omega = 1.0 / cfg["tau"]
     shape = (nz, ny, nx)
 
+    fp16 = cfg.get("storage", 0) == 1
+
     def f_at(x, y, z):
         flat = np.full(27, (z * ny + y) * nx + x)
-        return w + LI.random_deviations_at(SEED, shape, np.arange(27), flat, AMP).astype(np.float64)
+        g0 = LI.random_deviations_at(SEED, shape, np.arange(27), flat, AMP)
+        return w + (_fp16_stored(g0) if fp16 else g0.astype(np.float64))
 
     def collided(x, y, z):
         a = O.force_at(ocfg, amps[0], x, y, z, s)
@@ -120,14 +138,29 @@ def _sampled_step_parity(P, O, name, s):
     got = out[:, pz, py, px].T.cpu().numpy().astype(np.float64)
     g_in_max = AMP * max(LI.DEV_SHELL_SCALE)
     tol = 64 * 2.0 ** -24 * (g_in_max + np.abs(expect).max())
-    err = np.abs(got - expect).max()
-    _log(f"{len(pick)} sampled nodes x 27 populations: max abs error {err:.3e} (tolerance {tol:.3e})")
-    assert err <= tol
+    if fp16:  # one FP16 rounding of each stored output: half an ulp of g 2^k, relative 2^-11
+        tol = tol + 2.0 ** -11 * np.abs(expect)
+    err = np.abs(got - expect)
+    _log(f"{len(pick)} sampled nodes x 27 populations (storage {cfg.get('storage', 0)}, pattern {cfg.get('pattern', 0)}): max abs error {err.max():.3e} "
+         f"(max tolerance {np.max(tol):.3e}, worst ratio {np.max(err / tol):.3f})")
+    assert np.all(err <= tol)
 
 
 def test_turbulent_pipe_one_step_sampled_parity(P, oracle_mod):
     # s = 301: sin(2 pi s / T) ~ 1 with T = 1206, trigger force at full strength
     _sampled_step_parity(P, oracle_mod, "turbulent", 301)
+
+
+def test_turbulent_pipe_fp16_one_step_sampled_parity(P, oracle_mod):
+    """FP16 storage, as the bench's fp16 leg (its default launch geometry)."""
+    _sampled_step_parity(P, oracle_mod, "turbulent", 301, storage=1)
+
+
+@pytest.mark.parametrize("s", [301, 302])
+def test_turbulent_pipe_aa_one_step_sampled_parity(P, oracle_mod, s):
+    """AA pattern in place, as the bench's aa leg, from an odd (exchanged
+    slots) and an even (own slots) step index."""
+    _sampled_step_parity(P, oracle_mod, "turbulent", s, pattern=1)
 
 
 def test_paper_pipe_one_step_sampled_parity(P, oracle_mod):
