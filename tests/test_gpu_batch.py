@@ -142,3 +142,25 @@ def test_choose_pattern_tunes_both_patterns(P, tmp_path):
     # the adjoint needs two buffers
     r3 = autotune.choose_pattern(dict(cfg, adjoint=1), amps, steps=2, cache_path=cache)
     assert r3["pattern"] == 0 and set(r3["by_pattern"]) == {0}
+
+
+def test_full_size_ensemble_in_the_bench_launch(P):
+    """The 64-pipe ensemble (64 x 64 x 256, R = 30, own seeded forcing each)
+    in the launch the autotuner picks for the bench: AA in place, 128
+    threads, 3 pipes per launch in pipe-major order, XCD eighths, replays of
+    a 50-step graph.  After 100 steps, density and velocity of pipes 0, 31
+    and 63 equal independent single-pipe runs (two buffers, default launch)
+    bitwise."""
+    cfg = LI.preset("batched")
+    amps = LI.preset_amplitudes(cfg)
+    ens = P.Pipe(dict(cfg, pattern=1), amps)
+    ens.set_launch(block=128, zchunk=1, xcd_remap=1, pipes_per_launch=3, pipe_major=1)
+    ens.step_graph(100, 50)
+    rho, u = ens.moments()
+    for b in (0, 31, 63):
+        one = P.Pipe(dict(cfg, batch=1), amps[b:b + 1])
+        one.step(100)
+        r1, u1 = one.moments()
+        assert torch.equal(rho[b], r1[0]) and torch.equal(u[b], u1[0]), b
+        del one
+    assert (ens.diagnostics()[:, 4] == 0).all()
