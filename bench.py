@@ -74,29 +74,37 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(cfg, amps, seconds=12.0, single_seconds=4.0):
-    """The FP64 oracle (as it stands) on a z-slab of the same pipe: same
-    cross-section, parameters and forcing, nz = 48, on all host threads;
-    and on one thread (a child process with OMP_NUM_THREADS=1, nz = 4)."""
+def cpu_single_thread(cfg, amps, seconds=4.0):
+    """The FP64 oracle on one thread: a child process with OMP_NUM_THREADS=1
+    (the oracle's thread count is fixed when its library loads) on a 4-plane
+    slab.  Called before this process touches the GPU."""
     import subprocess
-    rate, steps, nf, dt, threads = _oracle_rate(cfg, amps, 48, seconds)
-    out = {"value": rate, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-           "sample": f"{cfg['nx']}x{cfg['ny']}x48 slab of the same pipe (R={cfg['radius']}), "
-                     f"{steps} steps, {nf} fluid nodes, {dt:.1f} s",
-           "cpu_model": _cpu_model()}
     code = ("import json, sys; sys.path.insert(0, sys.argv[1]); import bench; "
             "r = bench._oracle_rate(json.loads(sys.argv[2]), json.loads(sys.argv[3]), 4, float(sys.argv[4])); "
             "print(json.dumps(r))")
     env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
         res = subprocess.run([sys.executable, "-c", code, ROOT, json.dumps(cfg),
-                              json.dumps(None if amps is None else [float(a) for a in amps]), str(single_seconds)],
+                              json.dumps(None if amps is None else [float(a) for a in amps]), str(seconds)],
                              env=env, capture_output=True, text=True, timeout=120)
         r1 = json.loads(res.stdout.strip().splitlines()[-1])
-        out["single_thread"] = {"value": r1[0], "threads": r1[4],
-                                "sample": f"{cfg['nx']}x{cfg['ny']}x4 slab, {r1[1]} steps, {r1[3]:.1f} s"}
+        return {"value": r1[0], "threads": r1[4],
+                "sample": f"{cfg['nx']}x{cfg['ny']}x4 slab, {r1[1]} steps, {r1[3]:.1f} s"}
     except (subprocess.SubprocessError, ValueError, IndexError) as e:
-        out["single_thread"] = {"error": str(e)[:200]}
+        return {"error": str(e)[:200]}
+
+
+def cpu_baseline(cfg, amps, seconds=12.0, single=None):
+    """The FP64 oracle (as it stands) on a z-slab of the same pipe: same
+    cross-section, parameters and forcing, nz = 48, on all host threads;
+    ``single``: the one-thread figure of cpu_single_thread."""
+    rate, steps, nf, dt, threads = _oracle_rate(cfg, amps, 48, seconds)
+    out = {"value": rate, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{cfg['nx']}x{cfg['ny']}x48 slab of the same pipe (R={cfg['radius']}), "
+                     f"{steps} steps, {nf} fluid nodes, {dt:.1f} s",
+           "cpu_model": _cpu_model()}
+    if single is not None:
+        out["single_thread"] = single
     return out
 
 
@@ -432,10 +440,20 @@ def main():
               "is not supported", file=sys.stderr)
         sys.exit(2)
 
+    import lbm_inputs as LI
+
+    # the oracle's one-thread rate runs in a child process: started before
+    # this process touches the GPU
+    single = None
+    if not args.no_cpu_baseline and not args.profile_steps and not args.copy_calibration:
+        c0 = LI.preset(args.workload)
+        if args.wall is not None:
+            c0["wall"] = args.wall
+        single = cpu_single_thread(c0, LI.preset_amplitudes(c0)[0])
+
     import numpy as np
     import torch
 
-    import lbm_inputs as LI
     import paper_2405_12082_amd as P
 
     if not torch.cuda.is_available():
@@ -571,7 +589,7 @@ def main():
         out["extra"] = extra
     if not args.no_cpu_baseline:
         c1 = dict(cfg)
-        out["cpu_baseline"] = cpu_baseline(c1, amps[0], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(c1, amps[0], args.cpu_seconds, single)
     print(json.dumps(out), flush=True)
 
 
