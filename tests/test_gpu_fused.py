@@ -128,6 +128,18 @@ def test_two_step_launches_equal_single_steps(P, storage, zchunk):
     _log(f"storage {storage} zchunk {zchunk}: two-step launches == single steps over {one.step_index} steps")
 
 
+@pytest.mark.parametrize("nz,zchunk", [(1, 1), (1, 32), (2, 1), (2, 32), (3, 2)])
+def test_short_pipes(P, nz, zchunk):
+    """Pipes of 1, 2 and 3 planes (the periodic z neighbours of a plane
+    coincide or wrap within one z-range): 6 steps equal single steps
+    bitwise."""
+    cfg = _cfg(nz=nz)
+    one, two = _pair(P, cfg, _amps(cfg), dict(steps_per_launch=2, zchunk=zchunk))
+    one.step(6)
+    two.step(6)
+    assert np.array_equal(_pops(one), _pops(two))
+
+
 def test_periodic_box_smaller_than_a_tile(P):
     """12 x 10 periodic box (no wall): the 16 x 16 box of the only tile wraps
     onto its own columns; 9 steps equal single steps bitwise."""
