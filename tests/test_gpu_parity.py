@@ -115,14 +115,16 @@ def _amps(cfg, seed=5, boost=1.0):
     return LI.batch_amplitudes(seed, cfg["batch"], cfg["n_modes"], cfg["u_tau"], cfg["period"]) * boost
 
 
-@pytest.mark.parametrize("zchunk,block", [(4, 256), (1, 64), (5, 128)])
-def test_single_step_random_state_all_populations(gpu, O, zchunk, block):
+@pytest.mark.parametrize("zchunk,block,nz", [(4, 256, 13), (1, 64, 13), (5, 128, 13), (1, 256, 1), (4, 512, 1),
+                                             (2, 128, 2), (1, 64, 2)])
+def test_single_step_random_state_all_populations(gpu, O, zchunk, block, nz):
     """One fused step from seeded random deviations with the trigger force
     active (step index 10, sin(2 pi 10/40) = 1): every population of every
-    fluid node matches the oracle's collide + stream."""
-    cfg = _forced_cfg(zchunk=zchunk, block=block)
+    fluid node matches the oracle's collide + stream; also on pipes of one
+    and two planes, where the periodic z neighbours of a plane coincide."""
+    cfg = _forced_cfg(zchunk=zchunk, block=block, nz=nz)
     amps = _amps(cfg, boost=40.0)
-    _log(f"single step parity zchunk={zchunk} block={block}")
+    _log(f"single step parity zchunk={zchunk} block={block} nz={nz}")
     mask = _fluid(O, cfg)
     g0 = LI.random_deviations(123, (cfg["nz"], cfg["ny"], cfg["nx"]))
     g0[:, ~mask] = 0.0
