@@ -48,16 +48,19 @@ def _pops(p):
     return p.populations().cpu().numpy()
 
 
-@pytest.mark.parametrize("s0,zchunk,block", [(10, 4, 256), (11, 4, 256), (11, 1, 64), (10, 5, 128)])
-def test_aa_single_step_random_state_vs_oracle(P, oracle_mod, s0, zchunk, block):
+@pytest.mark.parametrize("s0,zchunk,block,nz", [(10, 4, 256, 13), (11, 4, 256, 13), (11, 1, 64, 13), (10, 5, 128, 13),
+                                                (10, 1, 256, 1), (11, 1, 256, 1), (10, 2, 128, 2), (11, 1, 64, 2)])
+def test_aa_single_step_random_state_vs_oracle(P, oracle_mod, s0, zchunk, block, nz):
     """One step from seeded random deviations written at an even (own slots)
     or odd (exchanged slots) step index: every population of every fluid
     node matches the oracle's collide + stream, within
-    64 * 2^-24 * (max|g_in| + max|g_out|)."""
+    64 * 2^-24 * (max|g_in| + max|g_out|); also on pipes of one and two
+    planes (the odd step's pushes along z land in the same or the other
+    plane)."""
     O = oracle_mod
-    cfg = _cfg(pattern=1, zchunk=zchunk, block=block)
+    cfg = _cfg(pattern=1, zchunk=zchunk, block=block, nz=nz)
     amps = _amps(cfg, boost=40.0)
-    _log(f"AA single step s0={s0} zchunk={zchunk} block={block}")
+    _log(f"AA single step s0={s0} zchunk={zchunk} block={block} nz={nz}")
     mask = O.Pipe(O.make_config(**cfg)).fluid_mask()
     g0 = LI.random_deviations(321, (cfg["nz"], cfg["ny"], cfg["nx"]))
     g0[:, ~mask] = 0.0
