@@ -55,12 +55,14 @@ def _vel_err(u_gpu, u_orc, mask):
     return np.abs(u_gpu - u_orc)[:, mask].max() / np.abs(u_orc[:, mask]).max()
 
 
-@pytest.mark.parametrize("nx,ny,radius,zchunk,block", [
-    (21, 23, 9.6, 4, 256), (21, 23, 9.3, 1, 64), (21, 23, 8.45, 5, 128),
+@pytest.mark.parametrize("nx,ny,radius,zchunk,block,nz", [
+    (21, 23, 9.6, 4, 256, 13), (21, 23, 9.3, 1, 64, 13), (21, 23, 8.45, 5, 128, 13),
     # thin pipes: links whose far node is solid (bounce-back fallback of
     # Eq. (fbc2)) and nodes with two cut links on one line (coupled inverse)
-    (7, 7, 1.1, 4, 64), (6, 7, 1.3, 2, 64)])
-def test_bouzidi_single_step_random_state(P, oracle_mod, nx, ny, radius, zchunk, block):
+    (7, 7, 1.1, 4, 64, 13), (6, 7, 1.3, 2, 64, 13),
+    # one and two planes: the far node x + c_i of a c_z link wraps onto the same or the other plane
+    (21, 23, 9.6, 1, 256, 1), (21, 23, 8.45, 2, 128, 2)])
+def test_bouzidi_single_step_random_state(P, oracle_mod, nx, ny, radius, zchunk, block, nz):
     """One step from seeded random deviations with the trigger force active:
     every population of every fluid node matches the oracle's collide +
     stream with the interpolated wall.  The radii give different cut-link
@@ -68,9 +70,9 @@ def test_bouzidi_single_step_random_state(P, oracle_mod, nx, ny, radius, zchunk,
     the 21x23 sections), and on the thin pipes the far-node fallback and the
     coupled inverse in set_populations."""
     O = oracle_mod
-    cfg = _cfg(nx=nx, ny=ny, radius=radius, zchunk=zchunk, block=block)
+    cfg = _cfg(nx=nx, ny=ny, radius=radius, zchunk=zchunk, block=block, nz=nz)
     amps = _amps(cfg, boost=40.0)
-    _log(f"Bouzidi single step R={radius} zchunk={zchunk} block={block}")
+    _log(f"Bouzidi single step R={radius} zchunk={zchunk} block={block} nz={nz}")
     mask = O.Pipe(O.make_config(**cfg)).fluid_mask()
     g0 = LI.random_deviations(77, (cfg["nz"], cfg["ny"], cfg["nx"]))
     g0[:, ~mask] = 0.0
