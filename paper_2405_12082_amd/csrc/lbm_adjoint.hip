@@ -158,32 +158,31 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
     const Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
-    const float *fs = g.fshape + (size_t)b * 3 * g.P;
-    const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
-    const float sig = (a.cursor >= 0 && a.cursor < g.n_sigma) ? g.sigma[a.cursor] : 0.f;
+    using W = typename RealOf<T>::type;  // the forward step's arithmetic type
+    const Shape<W> sh = shape_of<W>(g, b, k);
+    const W sig = sigma_of<W>(g, a.cursor);
     const R *lin = (const R *)a.lam_in + (size_t)b * g.pipe;
     R *lout = (R *)a.lam_out + (size_t)b * g.pipe;
-    const R om1 = R(1) - R(g.omega);
+    const R om1 = R(1) - R(omega_of<W>(g));
     const R we = R(a.energy_weight);
     double G[3] = {0.0, 0.0, 0.0};
     const int z0 = zc * t.zchunk, z1 = min(z0 + t.zchunk, g.nz);
     for (int z = z0; z < z1; ++z) {
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        using W = typename RealOf<T>::type;
         W v[27];
         gather<T, FORM_S, WALL>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
-        const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
+        // the forward's z factors, for the projection of the sensitivities
+        double cz, sz;
+        if constexpr (sizeof(W) == 8) {
+            cz = g.ztab64[z];
+            sz = g.ztab64[g.nz + z];
+        } else {
+            cz = (double)g.ztab[z];
+            sz = (double)g.ztab[g.nz + z];
+        }
         // the forward step's body acceleration (computed in its arithmetic type W), then promoted
         W fax, fay, faz;
-        if constexpr (sizeof(W) == 4) {
-            fax = sig * cz * px;
-            fay = sig * cz * py;
-            faz = g.accel_z + sig * sz * pq;
-        } else {
-            fax = W(sig) * W(cz) * W(px);
-            fay = W(sig) * W(cz) * W(py);
-            faz = W(g.accel_z) + W(sig) * W(sz) * W(pq);
-        }
+        body_force<W>(g, z, sig, sh.px, sh.py, sh.pq, fax, fay, faz);
         const R ax = R(fax), ay = R(fay), az = R(faz);
         R dr = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
@@ -236,9 +235,9 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const R sy = h * rho * s.Say + Qay + h * Luy;
         const R sz_ = h * rho * s.Saz + Qaz + h * Luz;
         write_lambda<R>(lout, g.pstride, (size_t)z * g.P + k, Ldr, Ljx, Ljy, Ljz, Dp);
-        G[0] += (double)cz * (double)sx;
-        G[1] += (double)cz * (double)sy;
-        G[2] += (double)sz * (double)sz_;
+        G[0] += cz * (double)sx;
+        G[1] += cz * (double)sy;
+        G[2] += sz * (double)sz_;
     }
     double *gp = a.grad_part + (((size_t)b * t.nzc + zc) * g.P + k) * 3;
     gp[0] = G[0];

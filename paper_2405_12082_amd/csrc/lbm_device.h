@@ -448,45 +448,73 @@ __device__ __forceinline__ R feq_dev(R dr, const Axis<R> &X, const Axis<R> &Y, c
 }
 
 // ---------------------------------------------------------------- forcing
+// Force inputs in the arithmetic type R: FP32 tables for FP32 and FP16
+// storage, the FP64 copies for FP64 storage (which computes in FP64
+// throughout, omega and h included).
 // time factor sigma(n) = sin(2 pi n / T) of the trigger force, 0 once it is off
-__device__ __forceinline__ float sigma_of(const Geom &g, long long n)
+template <typename R = float>
+__device__ __forceinline__ R sigma_of(const Geom &g, long long n)
 {
-    return (n >= 0 && n < g.n_sigma) ? g.sigma[n] : 0.f;
+    if constexpr (sizeof(R) == 8)
+        return (n >= 0 && n < g.n_sigma) ? g.sigma64[n] : 0.0;
+    else
+        return (n >= 0 && n < g.n_sigma) ? g.sigma[n] : 0.f;
+}
+// trigger shape sums (P_x, P_y, Q) of column k of pipe b
+template <typename R> struct Shape {
+    R px, py, pq;
+};
+template <typename R = float>
+__device__ __forceinline__ Shape<R> shape_of(const Geom &g, int b, int k)
+{
+    if constexpr (sizeof(R) == 8) {
+        const double *fs = g.fshape64 + (size_t)b * 3 * g.P;
+        return Shape<R>{fs[k], fs[g.P + k], fs[2 * g.P + k]};
+    } else {
+        const float *fs = g.fshape + (size_t)b * 3 * g.P;
+        return Shape<R>{fs[k], fs[g.P + k], fs[2 * g.P + k]};
+    }
+}
+template <typename R> __device__ __forceinline__ R omega_of(const Geom &g)
+{
+    if constexpr (sizeof(R) == 8)
+        return g.omega64;
+    else
+        return g.omega;
 }
 
 __device__ __forceinline__ int wrap_m(int z, int nz) { return z == 0 ? nz - 1 : z - 1; }
 __device__ __forceinline__ int wrap_p(int z, int nz) { return z == nz - 1 ? 0 : z + 1; }
 
-// body acceleration a(x, n) = h z^ + sigma(n) (C_z P_x, C_z P_y, S_z Q), in the
-// arithmetic type (FP32 tables promoted for FP64 storage)
+// body acceleration a(x, n) = h z^ + sigma(n) (C_z P_x, C_z P_y, S_z Q)
 template <typename R>
-__device__ __forceinline__ void body_force(const Geom &g, int z, float sig, float px, float py, float pq, R &ax, R &ay,
-                                           R &az)
+__device__ __forceinline__ void body_force(const Geom &g, int z, R sig, R px, R py, R pq, R &ax, R &ay, R &az)
 {
-    const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
     if constexpr (sizeof(R) == 4) {
+        const float cz = g.ztab[z], sz = g.ztab[g.nz + z];
         ax = sig * cz * px;
         ay = sig * cz * py;
         az = g.accel_z + sig * sz * pq;
     } else {
-        ax = R(sig) * R(cz) * R(px);
-        ay = R(sig) * R(cz) * R(py);
-        az = R(g.accel_z) + R(sig) * R(sz) * R(pq);
+        const double cz = g.ztab64[z], sz = g.ztab64[g.nz + z];
+        ax = sig * cz * px;
+        ay = sig * cz * py;
+        az = g.accel_z64 + sig * sz * pq;
     }
 }
 
 // One node's collision at a(x, n): moments, equilibrium, forcing and the
 // relaxation, in place on the gathered deviations v.
 template <typename T>
-__device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27], float sig, float px, float py,
-                                        float pq, int z)
+__device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27],
+                                        typename RealOf<T>::type sig, const Shape<typename RealOf<T>::type> &sh, int z)
 {
     using R = typename RealOf<T>::type;
     R ax, ay, az;
-    body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
+    body_force<R>(g, z, sig, sh.px, sh.py, sh.pq, ax, ay, az);
     const Moments<R> m = moments_of<R>(v);
     R ux, uy, uz;
-    const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, R(g.omega), ux, uy, uz);
+    const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, omega_of<R>(g), ux, uy, uz);
     post_collision_all<R>(c, v);
 }
 

@@ -129,10 +129,9 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
     const bool owned = valid && (code & FUSED_OWNED);
     const int k = valid ? (code & ~FUSED_OWNED) : 0;
     const Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
-    const float *fs = g.fshape + (size_t)b * 3 * g.P;
-    const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
+    const Shape<float> sh = shape_of<float>(g, b, k);
     const long long n = *g.step_dev + step_off;
-    const float sig1 = sigma_of(g, n), sig2 = sigma_of(g, n + 1);
+    const float sig1 = sigma_of<float>(g, n), sig2 = sigma_of<float>(g, n + 1);
     char *pout = reinterpret_cast<char *>(dst + (size_t)b * g.pipe);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const int z0 = zc * t.zchunk;
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
             const unsigned zo = (unsigned)zs * rowb;
             const unsigned zmo = (unsigned)wrap_m(zs, g.nz) * rowb, zpo = (unsigned)wrap_p(zs, g.nz) * rowb;
             gather<T, FORM_S, false>(p, zo, zmo, zpo, v);
-            collide<T>(g, v, sig1, px, py, pq, zs);
+            collide<T>(g, v, sig1, sh, zs);
             storage_round<T>(v);
         }
         __syncthreads();
@@ -173,7 +172,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
                           ROW_0 + 8 * ((j + 1) & 1)};
             float w[27];
             pull_lds(lds, s, p.wall, r, bb, r0_1, r5_2, r6_0, w);
-            collide<T>(g, w, sig2, px, py, pq, zq);
+            collide<T>(g, w, sig2, sh, zq);
             store_all<T>(pout, p.pbytes, (unsigned)zq * rowb + p.own, w);
         }
         zs = wrap_p(zs, g.nz);

@@ -23,6 +23,12 @@ struct Geom {
     const long long *step_dev;  // device step counter (graph-safe)
     const double *bcoef;        // [9][P] interpolated-wall coefficients (see pull_one), null: bounce-back
     float omega, accel_z;
+    // FP64 storage computes in FP64 throughout: its own copies of the force
+    // tables and of omega and h (null / unused for FP32 and FP16 storage)
+    const double *fshape64;  // [B][3][P]
+    const double *ztab64;    // [2][nz]
+    const double *sigma64;   // [n_sigma]
+    double omega64, accel_z64;
 };
 
 // tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe
@@ -107,7 +113,7 @@ int persistent_blocks_per_cu(int storage, int aa, int wall, int block);
 hipError_t launch_stream_copy(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, hipStream_t s);
 hipError_t launch_observe(int storage, int form, const Geom &g, const Tiles &t, const void *state, const ObserveArgs &o,
                           int step_off, hipStream_t s);
-hipError_t launch_init(int storage, int form, const Geom &g, const float *u0, void *state, hipStream_t s);
+hipError_t launch_init(int storage, int form, const Geom &g, const double *u0, void *state, hipStream_t s);
 hipError_t launch_set_pops(int storage, int form, const Geom &g, const float *pops, void *state, hipStream_t s);
 hipError_t launch_ring(int storage, int form, const Geom &g, const RingArgs &r, const void *state, float *ring,
                        hipStream_t s);

@@ -69,9 +69,9 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
 {
     const int k = tc.k;
     const Pull<T, WALL> p = make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
-    const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
-    const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
-    const float sig = sigma_of(g, n);
+    using R = typename RealOf<T>::type;
+    const Shape<R> sh = shape_of<R>(g, tc.b, k);
+    const R sig = sigma_of<R>(g, n);
     char *pout = reinterpret_cast<char *>(dst + (size_t)tc.b * g.pipe);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const int z0 = tc.zc * t.zchunk;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
         const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
         typename RealOf<T>::type v[27];
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
-        collide<T>(g, v, sig, px, py, pq, z);
+        collide<T>(g, v, sig, sh, z);
         if constexpr (MODE == STEP_AB)
             store_all<T>(pout, p.pbytes, zo + p.own, v);
         else if constexpr (MODE == STEP_AA_EVEN)
@@ -271,27 +271,26 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     const int k = tc.k;
     const bool active = k < g.ncol;
     const long long n = *g.step_dev + step_off;
-    const float sig = sigma_of(g, n);
+    using R = typename RealOf<T>::type;
+    const R sig = sigma_of<R>(g, n);
     double dsum[5] = {0, 0, 0, 0, 0};
     double esum[1] = {0};
     double psum[4] = {0, 0, 0, 0};
     int cnt = 0;
     if (active) {
         const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
-        const float *fs = g.fshape + (size_t)tc.b * 3 * g.P;
-        const float px = fs[k], py = fs[g.P + k], pq = fs[2 * g.P + k];
+        const Shape<R> sh = shape_of<R>(g, tc.b, k);
         const unsigned xy = g.colxy[k];
         const int x = xy & 0xffff, y = xy >> 16;
         const size_t plane = (size_t)g.nx * g.ny;
         const unsigned rowb = (unsigned)g.P * sizeof(T);
         const int z0 = tc.zc * t.zchunk;
         const int z1 = min(z0 + t.zchunk, g.nz);
-        using R = typename RealOf<T>::type;
         for (int z = z0; z < z1; ++z) {
             R v[27];
             gather<T, FORM, WALL>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
             R ax, ay, az;
-            body_force<R>(g, z, sig, px, py, pq, ax, ay, az);
+            body_force<R>(g, z, sig, sh.px, sh.py, sh.pq, ax, ay, az);
             const Moments<R> m = moments_of<R>(v);
             const R rho = R(1) + m.dr;
             const R inv = rcp_r(rho);
@@ -446,12 +445,12 @@ struct SrcDense {  // populations [27][nz][ny][nx] of one pipe (float)
     }
 };
 
-struct SrcEq {  // f^eq(1, (0, 0, u0(column))) - w
-    const float *u0;
+struct SrcEq {  // f^eq(1, (0, 0, u0(column))) - w, in FP64
+    const double *u0;
     template <int D> __device__ double get(int col, int) const
     {
         const Axis<double> zero = axis_factors(0.0);
-        return feq_dev<D, double>(0.0, zero, zero, axis_factors((double)u0[col]));
+        return feq_dev<D, double>(0.0, zero, zero, axis_factors(u0[col]));
     }
 };
 
@@ -500,7 +499,7 @@ __device__ __forceinline__ void write_slots(T *pipe, const Geom &g, const int (&
 
 // initial state f = f^eq(1, (0, 0, u0(r))) (u0 = 0: rest)
 template <typename T, int FORM>
-__global__ __launch_bounds__(256) void k_init(const Geom g, const float *__restrict__ u0, T *__restrict__ state)
+__global__ __launch_bounds__(256) void k_init(const Geom g, const double *__restrict__ u0, T *__restrict__ state)
 {
     const long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long total = (long long)g.B * g.nz * g.ncol;
@@ -736,7 +735,7 @@ static dim3 node_grid(const Geom &g)
 }
 
 template <typename T>
-static void init_form(int form, const Geom &g, const float *u0, void *state, hipStream_t s)
+static void init_form(int form, const Geom &g, const double *u0, void *state, hipStream_t s)
 {
     if (form == FORM_N)
         hipLaunchKernelGGL((k_init<T, FORM_N>), node_grid(g), dim3(256), 0, s, g, u0, (T *)state);
@@ -745,7 +744,7 @@ static void init_form(int form, const Geom &g, const float *u0, void *state, hip
     else
         hipLaunchKernelGGL((k_init<T, FORM_S>), node_grid(g), dim3(256), 0, s, g, u0, (T *)state);
 }
-hipError_t launch_init(int storage, int form, const Geom &g, const float *u0, void *state, hipStream_t s)
+hipError_t launch_init(int storage, int form, const Geom &g, const double *u0, void *state, hipStream_t s)
 {
     if (storage == 2)
         init_form<double>(form, g, u0, state, s);

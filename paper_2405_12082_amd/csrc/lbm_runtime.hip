@@ -54,6 +54,7 @@ struct Layout {
     size_t state_bytes = 0;
     // workspace offsets
     size_t off_state[2], off_box, off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
+    size_t off_fshape64, off_ztab64, off_sigma64;  // FP64 storage only
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_grad_base, off_modes;
     size_t off_ring_nodes, off_ring_idx, off_ring_w, off_twiddle;
@@ -181,7 +182,11 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_fshape = take(B * 3 * P * sizeof(float));
     L.off_ztab = take(2 * (size_t)c.nz * sizeof(float));
     L.off_sigma = take((size_t)L.n_sigma * sizeof(float));
-    L.off_u0 = take(P * sizeof(float));
+    L.off_u0 = take(P * sizeof(double));
+    const bool fp64 = c.storage == 2;
+    L.off_fshape64 = fp64 ? take(B * 3 * P * sizeof(double)) : 0;
+    L.off_ztab64 = fp64 ? take(2 * (size_t)c.nz * sizeof(double)) : 0;
+    L.off_sigma64 = fp64 ? take((size_t)L.n_sigma * sizeof(double)) : 0;
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
     L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
@@ -526,6 +531,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
                 }
     // trigger-force shape sums per pipe and per column, Eq. (TurbForce)
     std::vector<float> fshape(B * 3 * P, 0.f);
+    std::vector<double> fshape64(B * 3 * P, 0.0);
     std::vector<double> modes((size_t)2 * kMaxModes * 3 * P, 0.0);
     for (int k = 0; k < L.ncol; ++k)
         for (int q = 0; q < 2 * g.n_modes; ++q) {
@@ -541,20 +547,29 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
                 double v = 0.0;
                 for (int q = 0; q < 2 * g.n_modes; ++q) v += amps[b * 2 * g.n_modes + q] * modes[((size_t)q * 3 + d) * P + k];
                 fshape[(b * 3 + d) * P + k] = (float)v;
+                fshape64[(b * 3 + d) * P + k] = v;
             }
     std::vector<float> ztab(2 * (size_t)g.nz);
+    std::vector<double> ztab64(2 * (size_t)g.nz);
     for (int z = 0; z < g.nz; ++z) {
         const double ph = g.kz * 2.0 * M_PI * z / (double)g.nz;
-        ztab[z] = (float)std::cos(ph);
-        ztab[g.nz + z] = (float)std::sin(ph);
+        ztab64[z] = std::cos(ph);
+        ztab64[g.nz + z] = std::sin(ph);
+        ztab[z] = (float)ztab64[z];
+        ztab[g.nz + z] = (float)ztab64[g.nz + z];
     }
     std::vector<float> sig((size_t)L.n_sigma);
-    for (long long n = 0; n < L.n_sigma; ++n) sig[n] = (float)std::sin(2.0 * M_PI * (double)n / g.period);
-    std::vector<float> u0(P, 0.f);
+    std::vector<double> sig64(g.storage == 2 ? (size_t)L.n_sigma : 0);
+    for (long long n = 0; n < L.n_sigma; ++n) {
+        const double v = std::sin(2.0 * M_PI * (double)n / g.period);
+        sig[n] = (float)v;
+        if (g.storage == 2) sig64[n] = v;
+    }
+    std::vector<double> u0(P, 0.0);
     if (g.init == 1)
         for (int k = 0; k < L.ncol; ++k) {
             const double dx = L.colx[k] - 0.5 * (g.nx - 1), dy = L.coly[k] - 0.5 * (g.ny - 1);
-            u0[k] = (float)loglaw(g, std::sqrt(dx * dx + dy * dy));
+            u0[k] = loglaw(g, std::sqrt(dx * dx + dy * dy));
         }
 
     char *ws = c->ws;
@@ -571,7 +586,10 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     if (e == hipSuccess) e = h2d(L.off_fshape, fshape.data(), fshape.size() * sizeof(float));
     if (e == hipSuccess) e = h2d(L.off_ztab, ztab.data(), ztab.size() * sizeof(float));
     if (e == hipSuccess) e = h2d(L.off_sigma, sig.data(), sig.size() * sizeof(float));
-    if (e == hipSuccess) e = h2d(L.off_u0, u0.data(), u0.size() * sizeof(float));
+    if (e == hipSuccess) e = h2d(L.off_u0, u0.data(), u0.size() * sizeof(double));
+    if (e == hipSuccess && g.storage == 2) e = h2d(L.off_fshape64, fshape64.data(), fshape64.size() * sizeof(double));
+    if (e == hipSuccess && g.storage == 2) e = h2d(L.off_ztab64, ztab64.data(), ztab64.size() * sizeof(double));
+    if (e == hipSuccess && g.storage == 2) e = h2d(L.off_sigma64, sig64.data(), sig64.size() * sizeof(double));
     if (e == hipSuccess && g.adjoint) e = h2d(L.off_modes, modes.data(), modes.size() * sizeof(double));
     if (e != hipSuccess) {
         std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
@@ -600,13 +618,18 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     c->t2 = Tiles2{L.nt2, kDefaultZChunk2, (g.nz + kDefaultZChunk2 - 1) / kDefaultZChunk2, 1, 0, g.batch,
                    (const int *)(ws + L.off_box)};
     G.accel_z = (float)g.accel_z;
+    G.omega64 = 1.0 / g.tau;
+    G.accel_z64 = g.accel_z;
+    G.fshape64 = g.storage == 2 ? (const double *)(ws + L.off_fshape64) : nullptr;
+    G.ztab64 = g.storage == 2 ? (const double *)(ws + L.off_ztab64) : nullptr;
+    G.sigma64 = g.storage == 2 ? (const double *)(ws + L.off_sigma64) : nullptr;
 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_state[0], L.state_bytes, c->stream);  // padding reads as 0
     if (e == hipSuccess && L.off_state[1] != L.off_state[0]) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_prof_acc, B * P * 5 * sizeof(double), c->stream);
-    if (e == hipSuccess) e = launch_init(g.storage, c->form(0), G, (const float *)(ws + L.off_u0), c->state(0), c->stream);
+    if (e == hipSuccess) e = launch_init(g.storage, c->form(0), G, (const double *)(ws + L.off_u0), c->state(0), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
@@ -1011,9 +1034,9 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
         HIPCHK(c, launch_adjoint(c->cfg.storage, c->cfg.adjoint, c->geom, c->L.adj, a, c->stream));
         if (nq > 0) {
             const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
-            // the kernels use the FP32 table value of sigma; use the same rounding here
-            const double sig32 = (double)(float)sig;
-            if (sig32 != 0.0) HIPCHK(c, launch_grad_accumulate(c->geom, c->L.adj, a.grad_part, acc, sig32, c->stream));
+            // the forward used the FP32 table value of sigma (FP64 storage: the FP64 one); the same here
+            const double sigf = c->cfg.storage == 2 ? sig : (double)(float)sig;
+            if (sigf != 0.0) HIPCHK(c, launch_grad_accumulate(c->geom, c->L.adj, a.grad_part, acc, sigf, c->stream));
         }
         c->lam_cur ^= 1;
         c->cursor -= 1;

@@ -23,17 +23,17 @@ __global__ __launch_bounds__(256) void k_ring(const Geom g, const RingArgs r, co
     __shared__ float uz[kRingNodes];
     const int z = blockIdx.x % g.nz, b = blockIdx.x / g.nz;
     using R = typename RealOf<T>::type;
-    const float sig = sigma_of(g, *g.step_dev);
+    const R sig = sigma_of<R>(g, *g.step_dev);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const unsigned zo = (unsigned)z * rowb, zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
-    const float *fs = g.fshape + (size_t)b * 3 * g.P;
     for (int u = threadIdx.x; u < r.n_nodes; u += 256) {
         const int col = r.nodes[u];
         const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col, g.bcoef);
         R v[27];
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         R ax, ay, az;
-        body_force<R>(g, z, sig, fs[col], fs[g.P + col], fs[2 * g.P + col], ax, ay, az);
+        const Shape<R> sh = shape_of<R>(g, b, col);
+        body_force<R>(g, z, sig, sh.px, sh.py, sh.pq, ax, ay, az);
         const Moments<R> m = moments_of<R>(v);
         uz[u] = (float)(m.jz * rcp_r(R(1) + m.dr) + R(0.5) * az);
     }

@@ -191,8 +191,10 @@ def test_periodic_box_shear_wave(gpu, O):
 
 # ------------------------------------------------------------------ FP64 reference storage
 def test_fp64_storage_forced_run(gpu, O):
-    """FP64 deviations and collision: the forced log-law run matches the
-    oracle to FP32 export precision after 50 steps (the forcing tables are FP32)."""
+    """FP64 deviations, collision and force tables: the forced log-law run
+    matches the oracle after 50 steps to FP32 export precision in the
+    populations and to rounding level in the FP64 channels (mass, momentum
+    and energy sums)."""
     cfg = _forced_cfg(nx=30, ny=28, nz=24, radius=13.4, storage=2)
     amps = _amps(cfg, seed=9)
     p = gpu.Pipe(cfg, amps)
@@ -208,9 +210,12 @@ def test_fp64_storage_forced_run(gpu, O):
     assert err < 2e-7  # the export rounds to FP32
     d = p.diagnostics(raise_on_nan=True)[0]
     s = o.sums()
-    assert abs(d[0] - s[0]) < 1e-10 * s[0]
-    # FP32 forcing tables (sigma, cos/sin, mode shapes): ~1e-9 on the summed momentum
-    np.testing.assert_allclose(d[1:4], s[1:4], rtol=1e-8, atol=1e-12 * s[0])
+    e, eo = p.energy()[0], o.energy()
+    mom = np.abs(d[1:4] - s[1:4]).max() / np.abs(s[1:4]).max()
+    _log(f"fp64 storage: mass {abs(d[0] - s[0]) / s[0]:.2e}, momentum {mom:.2e}, energy {abs(e - eo) / eo:.2e}")
+    assert abs(d[0] - s[0]) < 1e-12 * s[0]
+    assert mom < 1e-11
+    assert abs(e - eo) < 1e-11 * eo
 
 
 # ------------------------------------------------------------------ FP16 storage
