@@ -65,21 +65,23 @@ def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod, precision, wall, nz, st
     assert err < tol
 
 
-@pytest.mark.parametrize("precision,tol,wall", [("fp64", 1e-5, 0), ("fp32", 1e-4, 0), ("fp64", 1e-5, 1)])
-def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol, wall):
+@pytest.mark.parametrize("precision,tol,wall,storage", [("fp64", 1e-5, 0, 0), ("fp32", 1e-4, 0, 0), ("fp64", 1e-5, 1, 0),
+                                                      ("fp64", 1e-10, 0, 2), ("fp64", 1e-10, 1, 2)])
+def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol, wall, storage):
     """2000 steps of a 16x16x32 pipe (R = 7) with the adjoint workload's
-    physics: the GPU adjoint (FP32 forward) against the oracle's complex-step
-    tangent of the whole FP64 run (the exact derivative); wall = 1 with the
-    interpolated wall."""
+    physics: the GPU adjoint against the oracle's complex-step tangent of
+    the whole FP64 run (the exact derivative); wall = 1 with the
+    interpolated wall; storage 0: FP32 forward, 2: FP64 forward (rounding
+    level)."""
     O = oracle_mod
     cfg = LI.preset("adjoint")
     cfg.update(nx=16, ny=16, nz=32, radius=7.0, accel_z=2 * cfg["u_tau"] ** 2 / 7.0,
-               period=float(round(0.052 * 7.0 / cfg["u_tau"])), force_off_step=2000, wall=wall)
+               period=float(round(0.052 * 7.0 / cfg["u_tau"])), force_off_step=2000, wall=wall, storage=storage)
     amps = LI.preset_amplitudes(cfg)
     J, g = gpu.EnergyAdjoint(cfg, 1501, 2001, checkpoint_every=100, precision=precision).gradient(amps)
     Jt, gt = O.tangent_gradient(O.make_config(**cfg), amps[0], 1501, 2001)
     err = np.linalg.norm(g[0] - gt) / np.linalg.norm(gt)
-    _log(f"{precision} adjoint vs oracle tangent over 2000 steps: {err:.3e}")
+    _log(f"{precision} adjoint (storage {storage}) vs oracle tangent over 2000 steps: {err:.3e}")
     assert err < tol
 
 
