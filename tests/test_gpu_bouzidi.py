@@ -136,6 +136,11 @@ def test_bouzidi_forced_loglaw_run(P, oracle_mod, storage, tol):
     d = p.diagnostics(raise_on_nan=True)[0]
     s = o.sums()
     assert abs(d[0] - s[0]) <= (1e-9 if storage != 1 else 1e-5) * s[0]
+    if storage == 2:  # FP64 throughout: the FP64 sums at rounding level
+        mom = np.abs(d[1:4] - s[1:4]).max() / np.abs(s[1:4]).max()
+        e, eo = p.energy()[0], o.energy()
+        _log(f"FP64 storage: mass {abs(d[0] - s[0]) / s[0]:.2e}, momentum {mom:.2e}, energy {abs(e - eo) / eo:.2e}")
+        assert abs(d[0] - s[0]) < 1e-12 * s[0] and mom < 1e-11 and abs(e - eo) < 1e-11 * eo
 
 
 def test_bouzidi_graph_persistent_and_batch(P):
