@@ -366,6 +366,8 @@ def run_precision(steps=5000, sample_every=100, oracle_steps=100):
             p.step(target - n)
             n = target
             snaps[target] = p.moments()[1][0].cpu().numpy().astype(np.float64)
+            if storage == 2 and target == oracle_steps:  # the FP64 channels at the oracle step
+                fp64_sums = (p.diagnostics()[0].copy(), float(p.energy()[0]))
         p.profile_reset()
         while n < steps:
             k = min(sample_every - n % sample_every, steps - n)
@@ -382,7 +384,9 @@ def run_precision(steps=5000, sample_every=100, oracle_steps=100):
     o.step(oracle_steps)
     uo = o.moments()[1]
     mask = o.fluid_mask()
+    so, eo = o.sums(), o.energy()
     del o
+    d64, e64 = fp64_sums
     ref_snaps, ref_prof, _ = res[2]
 
     def verr(u, ur):
@@ -396,7 +400,12 @@ def run_precision(steps=5000, sample_every=100, oracle_steps=100):
         return float(d / np.abs(ref_prof[key][sel]).max()) if relative else float(d)
 
     out = {"pipe": "64x64x256 R=30", "steps": steps, "stats_window": [first, steps],
-           "fp64_gpu_vs_oracle_velocity": {f"step_{oracle_steps}": verr(ref_snaps[oracle_steps], uo)}}
+           "fp64_gpu_vs_oracle_velocity": {f"step_{oracle_steps}": verr(ref_snaps[oracle_steps], uo),
+                                           "through": "the FP32 moments export"},
+           "fp64_gpu_vs_oracle_sums": {"step": oracle_steps,
+                                       "mass": float(abs(d64[0] - so[0]) / so[0]),
+                                       "momentum": float(np.abs(d64[1:4] - so[1:4]).max() / np.abs(so[1:4]).max()),
+                                       "energy": float(abs(e64 - eo) / eo)}}
     for storage, name in ((0, "fp32"), (1, "fp16")):
         snaps, prof, ok = res[storage]
         out[name] = {"velocity_step_100": verr(snaps[100], ref_snaps[100]),
