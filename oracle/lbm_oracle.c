@@ -184,6 +184,13 @@ void orc_collide(const double f[27], const double a[3], double omega, double fs[
 {
     orc_collide_r(f, a, omega, fs, NULL, NULL);
 }
+void orc_feq2(double rho, const double u[3], double feq[27]) { orc_feq2_r(rho, u, feq); }
+void orc_force2(double rho, const double u[3], const double a[3], double F[27]) { orc_force2_r(rho, u, a, F); }
+void orc_collide_kind(const double f[27], const double a[3], double omega, int32_t collision,
+                      int32_t equilibrium, double fs[27])
+{
+    orc_collide_kind_r(f, a, omega, collision, equilibrium, fs, NULL, NULL);
+}
 static cplx mkc(const double *ri) { return ri[0] + I * ri[1]; }
 static void putc2(double *ri, cplx v)
 {
@@ -412,7 +419,10 @@ static void initial_state(orc_pipe *p)
                 if (c->init == 1 && c->radius > 0.0) {
                     const double dx = x - axis_x(c), dy = y - axis_y(c);
                     const double u[3] = {0.0, 0.0, loglaw_uz(c, sqrt(dx * dx + dy * dy))};
-                    orc_feq_r(1.0, u, f);
+                    if (c->equilibrium == 1)
+                        orc_feq2_r(1.0, u, f);
+                    else
+                        orc_feq_r(1.0, u, f);
                 } else {
                     for (int i = 0; i < 27; ++i) f[i] = ORC_W[i];
                 }
@@ -494,7 +504,8 @@ void orc_pipe_step(orc_pipe *p, int32_t nsteps)
                     if (!p->fluid[n]) continue;
                     double a[3];
                     node_force(p, n, tf, a);
-                    orc_collide_r(p->f + 27 * n, a, omega, p->fs + 27 * n, NULL, NULL);
+                    orc_collide_kind_r(p->f + 27 * n, a, omega, c->collision, c->equilibrium, p->fs + 27 * n,
+                                       NULL, NULL);
                 }
         /* streaming with the wall */
 #pragma omp parallel for schedule(static)
@@ -717,7 +728,7 @@ double orc_tangent_gradient(const orc_config *cfg, const double *amps, int64_t b
                 if (!p->fluid[n]) continue;
                 cplx a[3];
                 force_c(p, ms, n, tf, ac, a);
-                orc_collide_c(f + 27 * n, a, omega, fs + 27 * n, NULL, NULL);
+                orc_collide_kind_c(f + 27 * n, a, omega, c->collision, c->equilibrium, fs + 27 * n, NULL, NULL);
             }
 #pragma omp parallel for schedule(static)
             for (int z = 0; z < c->nz; ++z)
@@ -815,7 +826,7 @@ double orc_adjoint_gradient(const orc_config *cfg, const double *amps, int64_t b
                 double v = 0.0;
                 if (n + 1 < e) {
                     fc[j] += I * h;
-                    orc_collide_c(fc, a, omega, out, NULL, NULL);
+                    orc_collide_kind_c(fc, a, omega, c->collision, c->equilibrium, out, NULL, NULL);
                     fc[j] = f[j];
                     for (int k = 0; k < 27; ++k) v += cimag(out[k]) / h * m[k];
                 }
@@ -830,7 +841,7 @@ double orc_adjoint_gradient(const orc_config *cfg, const double *amps, int64_t b
                 cplx ad[3] = {a[0], a[1], a[2]};
                 ad[d] += I * h;
                 if (n + 1 < e) {
-                    orc_collide_c(fc, ad, omega, out, NULL, NULL);
+                    orc_collide_kind_c(fc, ad, omega, c->collision, c->equilibrium, out, NULL, NULL);
                     for (int k = 0; k < 27; ++k) sa[d] += cimag(out[k]) / h * m[k];
                 }
                 if (d == 2 && in_window(n, b, e)) sa[d] += Wn * cimag(energy_node_c(fc, ad[2], inv_nf)) / h;

@@ -32,6 +32,8 @@ typedef struct {
     int32_t wall;             /* 0: halfway bounce-back, 1: Bouzidi, Eqs. (fbc1)-(fbc2) */
     int32_t init;             /* 0: rest (f = w), 1: log-law mean profile (f = f^eq) */
     double u_tau;             /* friction velocity used by the log-law initial profile */
+    int32_t collision;        /* 0: MRT of the appendix (Eq. (m*)); 1: SRT/BGK, Eq. (srt) */
+    int32_t equilibrium;      /* 0: sixth-order Hermite equilibrium; 1: second-order (LBM-O(2)) */
 } orc_config;
 
 typedef struct orc_pipe orc_pipe;
@@ -44,6 +46,12 @@ void orc_feq(double rho, const double u[3], double feq[27]);
 void orc_meq(double rho, const double u[3], double meq[27]);
 void orc_rmrt(double rho, const double u[3], const double F[3], double R[27]);
 void orc_collide(const double f[27], const double a[3], double omega, double fs[27]);
+/* second-order equilibrium and its forcing term (comparison scheme), and the
+ * collision of a given kind (collision, equilibrium as in orc_config) */
+void orc_feq2(double rho, const double u[3], double feq[27]);
+void orc_force2(double rho, const double u[3], const double a[3], double F[27]);
+void orc_collide_kind(const double f[27], const double a[3], double omega, int32_t collision,
+                      int32_t equilibrium, double fs[27]);
 /* complex-step variants: arguments are interleaved (re, im) pairs */
 void orc_feq_cplx(const double rho[2], const double u[6], double feq[54]);
 void orc_meq_cplx(const double rho[2], const double u[6], double meq[54]);

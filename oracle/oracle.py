@@ -26,6 +26,7 @@ class OrcConfig(C.Structure):
         ("l_frac", C.c_double), ("period", C.c_double),
         ("force_off_step", C.c_int64),
         ("wall", C.c_int32), ("init", C.c_int32), ("u_tau", C.c_double),
+        ("collision", C.c_int32), ("equilibrium", C.c_int32),
     ]
 
 
@@ -33,7 +34,7 @@ def make_config(**kw) -> OrcConfig:
     """Oracle configuration from keyword values (unknown keys are ignored)."""
     defaults = dict(nx=24, ny=24, nz=48, radius=10.0, tau=0.8, accel_z=0.0, n_modes=0,
                     kz=3.0, kappa=0.5, l0_frac=0.2, l_frac=0.4, period=1.0,
-                    force_off_step=0, wall=0, init=0, u_tau=0.0)
+                    force_off_step=0, wall=0, init=0, u_tau=0.0, collision=0, equilibrium=0)
     names = [f[0] for f in OrcConfig._fields_]
     vals = {k: kw.get(k, defaults[k]) for k in names}
     return OrcConfig(**vals)
@@ -59,6 +60,9 @@ def lib():
         L.orc_meq.argtypes = [C.c_double, dp, dp]
         L.orc_rmrt.argtypes = [C.c_double, dp, dp, dp]
         L.orc_collide.argtypes = [dp, dp, C.c_double, dp]
+        L.orc_feq2.argtypes = [C.c_double, dp, dp]
+        L.orc_force2.argtypes = [C.c_double, dp, dp, dp]
+        L.orc_collide_kind.argtypes = [dp, dp, C.c_double, C.c_int32, C.c_int32, dp]
         L.orc_feq_cplx.argtypes = [dp, dp, dp]
         L.orc_meq_cplx.argtypes = [dp, dp, dp]
         L.orc_collide_cplx.argtypes = [dp, dp, C.c_double, dp]
@@ -150,6 +154,31 @@ def collide(f, a, omega):
     f, a = _f64(f), _f64(a)
     out = np.zeros(27)
     lib().orc_collide(_p(f), _p(a), float(omega), _p(out))
+    return out
+
+
+def feq2(rho, u):
+    """Second-order equilibrium (the LBM-O(2) comparison scheme)."""
+    u = _f64(u)
+    out = np.zeros(27)
+    lib().orc_feq2(float(rho), _p(u), _p(out))
+    return out
+
+
+def force2(rho, u, a):
+    """Population forcing a . grad_u of the second-order equilibrium."""
+    u, a = _f64(u), _f64(a)
+    out = np.zeros(27)
+    lib().orc_force2(float(rho), _p(u), _p(a), _p(out))
+    return out
+
+
+def collide_kind(f, a, omega, collision=0, equilibrium=0):
+    """Collision of a given kind: collision 0 MRT / 1 SRT (BGK), equilibrium
+    0 sixth-order Hermite / 1 second order.  (0, 0) equals :func:`collide`."""
+    f, a = _f64(f), _f64(a)
+    out = np.zeros(27)
+    lib().orc_collide_kind(_p(f), _p(a), float(omega), int(collision), int(equilibrium), _p(out))
     return out
 
 
