@@ -95,6 +95,20 @@ typedef struct {
                              0 dispatch order; 1 XCD x takes the x-th eighth of the tiles;
                              G in 2..4096: XCD x takes every eighth chunk of G consecutive
                              tiles (neighbouring tiles share one XCD's L2) */
+    int32_t collision;    /* 0: the paper's multiple-relaxation-time collision (Eqs. (mrt),
+                             (lambda), (m*)); 1: the single-relaxation-time BGK operator of
+                             Eq. (srt), every population relaxed at omega = 1/tau, with
+                             f*_i = f_i - omega (f_i - f^eq_i) + (1 - omega/2) F_i
+                             (a comparison scheme) */
+    int32_t equilibrium;  /* 0: the sixth-order Hermite equilibrium of Eq.
+                             (BoltzmannEquilibriumDistribution); 1: the second-order one,
+                             f^eq_i = w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u), of the
+                             LBM-O(2) scheme compared with in Section III (Table I).  Forcing
+                             is F_i = a . grad_u f^eq_i with the chosen equilibrium.  Any
+                             choice other than (0, 0) needs FP32 or FP64 storage, the
+                             two-buffer pattern and no adjoint; it runs through lbm_step,
+                             lbm_step_graph and lbm_recompute (not the persistent or
+                             two-step launches) */
 } lbm_config;
 
 /* Layout facts of a configuration (host only, no GPU needed). */
@@ -113,7 +127,9 @@ typedef struct {
  * Errors: LBM_EINVAL for an invalid configuration (cfg NULL, sizes < 1,
  * tau <= 0.5, n_modes outside 0..6, period <= 0 with n_modes > 0, a
  * cross-section with no fluid column, radius > (min(nx,ny)-1)/2, unknown
- * storage/wall/pattern/init values, block/zchunk out of range). */
+ * storage/wall/pattern/init/collision/equilibrium values, block/zchunk out
+ * of range, a comparison scheme with FP16 storage, the AA pattern or an
+ * adjoint). */
 int lbm_describe(const lbm_config *cfg, lbm_layout *out);
 
 /* Device workspace size lbm_init needs for cfg.  Host only. */
@@ -141,7 +157,8 @@ int lbm_step(lbm_ctx *ctx, int32_t n);
  * launches for the remainder.  Async.  Same results as lbm_step. */
 int lbm_step_graph(lbm_ctx *ctx, int32_t n, int32_t k);
 
-/* Run n steps as ONE persistent cooperative launch: the co-resident
+/* Run n steps as ONE persistent cooperative launch (the paper's collision
+ * only: LBM_EINVAL for a comparison scheme): the co-resident
  * workgroups are split into groups that each own whole pipes; a group's
  * workgroups stride over its pipes' tiles and meet at a group barrier before
  * the next step (pipes are independent, so groups never wait for each
@@ -286,7 +303,6 @@ int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *
  * buffer is copied onto itself).  Async. */
 int lbm_stream_copy(lbm_ctx *ctx, int32_t n);
 
-/* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
 /* Coherent-structure identification, Section II.C.
  *
  * lbm_ring_sample: the streamwise velocity u_z (as lbm_moments reports it,
@@ -313,6 +329,7 @@ int lbm_ring_sample(lbm_ctx *ctx, double r0, int32_t ntheta, float *ring);
 int lbm_ring_spectrum(lbm_ctx *ctx, const float *ring, int32_t ntheta, int32_t mmax, double *spec, double *mean,
                       int32_t *dominant);
 
+/* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
 const char *lbm_last_error(const lbm_ctx *ctx);
 /* Release the context (not the caller's memory).  Synchronises its stream. */
 void lbm_destroy(lbm_ctx *ctx);

@@ -28,6 +28,7 @@ class LbmConfig(C.Structure):
         ("storage", C.c_int32), ("wall", C.c_int32), ("pattern", C.c_int32), ("init", C.c_int32),
         ("u_tau", C.c_double),
         ("adjoint", C.c_int32), ("block", C.c_int32), ("zchunk", C.c_int32), ("xcd_remap", C.c_int32),
+        ("collision", C.c_int32), ("equilibrium", C.c_int32),
     ]
 
 
@@ -43,7 +44,7 @@ class LbmLayout(C.Structure):
 CONFIG_DEFAULTS = dict(nx=24, ny=24, nz=48, batch=1, radius=10.0, tau=0.8, accel_z=0.0, n_modes=0,
                        kz=3.0, kappa=0.5, l0_frac=0.2, l_frac=0.4, period=1.0, force_off_step=0,
                        storage=0, wall=0, pattern=0, init=0, u_tau=0.0, adjoint=0, block=0, zchunk=0,
-                       xcd_remap=0)
+                       xcd_remap=0, collision=0, equilibrium=0)
 
 
 def make_config(**kw) -> LbmConfig:

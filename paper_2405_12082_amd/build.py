@@ -9,7 +9,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_runtime.hip", "lbm_kernels.hip", "lbm_fused.hip", "lbm_adjoint.hip", "lbm_structures.hip"]
+SOURCES = ["lbm_kernels.hip", "lbm_variants.hip", "lbm_runtime.hip", "lbm_fused.hip", "lbm_adjoint.hip",
+           "lbm_structures.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -19,7 +20,7 @@ def hipcc_flags():
             "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     csrc = os.path.join(HERE, "csrc")
     objs, procs = [], []
     for src in SOURCES:

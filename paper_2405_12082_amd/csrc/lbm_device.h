@@ -349,16 +349,30 @@ template <typename R> __device__ __forceinline__ Axis<R> axis_factors(R u)
 template <int C, typename R> __device__ __forceinline__ R dsel(const Axis<R> &a) { return C == 0 ? a.d0 : (C > 0 ? a.dp : a.dm); }
 template <int C, typename R> __device__ __forceinline__ R qsel(const Axis<R> &a) { return C == 0 ? a.q0 : (C > 0 ? a.qp : a.qm); }
 
+// Collision kinds.  KIND_MRT6 is the paper's scheme: the multiple-relaxation-
+// time collision of the appendix with the sixth-order Hermite equilibrium.
+// The others are the comparison schemes: the same MRT collision with the
+// second-order equilibrium of the LBM-O(2) scheme (Section III, Table I), and
+// the single-relaxation-time BGK operator of Eq. (srt) (every population
+// relaxed at omega) with either equilibrium.  All use Guo forcing in
+// population form, F_i = a . grad_u f^eq_i.
+enum CollisionKind : int { KIND_MRT6 = 0, KIND_MRT2 = 1, KIND_SRT6 = 2, KIND_SRT2 = 3 };
+__host__ __device__ constexpr bool kind_srt(int kind) { return kind >= KIND_SRT6; }
+__host__ __device__ constexpr bool kind_eq2(int kind) { return (kind & 1) != 0; }
+
 template <typename R> struct CollideCtx {
     Axis<R> X, Y, Z;
     R dr, rho;      // rho - 1 and rho
     R ax, ay, az;   // body acceleration
+    R ux, uy, uz;   // velocity u = j/rho + a/2
     R c4, c5, c6, c7, c8;   // (1 - omega) (m_k - m_k^eq + R_k/2), k = 4..8
+    R omega;
 };
 
 // Relaxed non-equilibrium part of the stress moments, Eq. (m*) with
 // Lam_k = omega for k = 4..8: m*_k - m^eq_k - R_k/2 = (1 - omega)(m_k - m^eq_k + R_k/2),
-// using the printed m_4..8^eq and R_4..8.
+// using the printed m_4..8^eq and R_4..8 (the second-order equilibrium has
+// the same second-order moments, so these hold for it too).
 template <typename R>
 __device__ __forceinline__ CollideCtx<R> collide_setup(const Moments<R> &m, R ax, R ay, R az, R omega, R &ux, R &uy,
                                                        R &uz)
@@ -366,11 +380,15 @@ __device__ __forceinline__ CollideCtx<R> collide_setup(const Moments<R> &m, R ax
     CollideCtx<R> c;
     c.dr = m.dr;
     c.rho = R(1) + m.dr;
+    c.omega = omega;
     const R inv = rcp_r(c.rho);
     // Eq. (macroscopic_u): u = j/rho + a/2
     ux = m.jx * inv + R(0.5) * ax;
     uy = m.jy * inv + R(0.5) * ay;
     uz = m.jz * inv + R(0.5) * az;
+    c.ux = ux;
+    c.uy = uy;
+    c.uz = uz;
     c.ax = ax;
     c.ay = ay;
     c.az = az;
@@ -395,8 +413,14 @@ __device__ __forceinline__ CollideCtx<R> collide_setup(const Moments<R> &m, R ax
 // R^MRT); d_k = columns 4..8 of the inverse moment matrix (sparse: edge links
 // for k = 4..6, face links for 7, 8).  The three populations of one in-plane
 // group (c_x, c_y) share the x-y factors.
-template <typename R, int G = 0>
-__device__ __forceinline__ void group_post_collision(const CollideCtx<R> &c, R hr, R f7, R f8, R f9, R (&g)[27])
+// Comparison schemes (KIND != KIND_MRT6): with the second-order equilibrium,
+// Pi_i - 1 = 3 c.u + 9/2 (c.u)^2 - 3/2 u.u and F_i/(2 w_i) = rho/2 (3 (c - u).a
+// + 9 (c.u)(c.a)); the BGK operator stores
+//   g*_i = (1 - omega) g_i + omega (f^eq_i - w_i) + (1 - omega/2) F_i
+// in place of the MRT sum (the same moments, every one relaxed at omega).
+template <typename R, int KIND, int G = 0>
+__device__ __forceinline__ void group_post_collision(const CollideCtx<R> &c, R hr, R f7, R f8, R f9, R usq15, R ua,
+                                                     R (&g)[27])
 {
     constexpr int cx = G % 3 - 1, cy = G / 3 - 1;
     const R dx = dsel<cx>(c.X), dy = dsel<cy>(c.Y);
@@ -405,36 +429,56 @@ __device__ __forceinline__ void group_post_collision(const CollideCtx<R> &c, R h
     const R e1 = R(1) + exy;
     const R A = hr * fma_r(c.ax * qx, R(1) + dy, c.ay * qy * (R(1) + dx));
     const R Bz = hr * c.az * e1;
+    // second-order equilibrium: in-plane parts of c.u and c.a
+    const R s = R(cx) * c.ux + R(cy) * c.uy;
+    const R sa = R(cx) * c.ax + R(cy) * c.ay;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         const int czr = t == 0 ? 0 : (t == 1 ? 1 : -1);
-        const R dz = czr == 0 ? c.Z.d0 : (czr > 0 ? c.Z.dp : c.Z.dm);
-        const R qz = czr == 0 ? c.Z.q0 : (czr > 0 ? c.Z.qp : c.Z.qm);
-        const R pim1 = fma_r(dz, e1, exy);
-        const R feq = fma_r(pim1, c.rho, c.dr);          // (rho Pi - 1)
-        const R fh = fma_r(qz, Bz, (R(1) + dz) * A);      // F / (2 w)
-        R corr = R(0);
-        const int shell = cx * cx + cy * cy + czr * czr;
-        if (shell == 1) corr = cx != 0 ? f7 : (cy != 0 ? f8 : f9);
-        if (shell == 2) {
-            if (czr == 0) corr = (cx * cy > 0 ? R(0.25) : R(-0.25)) * c.c4;
-            else if (cy == 0) corr = (cx * czr > 0 ? R(0.25) : R(-0.25)) * c.c5;
-            else corr = (cy * czr > 0 ? R(0.25) : R(-0.25)) * c.c6;
+        R feq, fh;  // (rho Pi - 1) and F / (2 w)
+        if constexpr (!kind_eq2(KIND)) {
+            const R dz = czr == 0 ? c.Z.d0 : (czr > 0 ? c.Z.dp : c.Z.dm);
+            const R qz = czr == 0 ? c.Z.q0 : (czr > 0 ? c.Z.qp : c.Z.qm);
+            const R pim1 = fma_r(dz, e1, exy);
+            feq = fma_r(pim1, c.rho, c.dr);
+            fh = fma_r(qz, Bz, (R(1) + dz) * A);
+        } else {
+            const R cu = czr == 0 ? s : (czr > 0 ? s + c.uz : s - c.uz);
+            const R ca = czr == 0 ? sa : (czr > 0 ? sa + c.az : sa - c.az);
+            const R pim1 = fma_r(cu, fma_r(R(4.5), cu, R(3)), usq15);
+            feq = fma_r(pim1, c.rho, c.dr);
+            fh = hr * fma_r(R(9) * cu, ca, R(3) * (ca - ua));
         }
         const int i = t == 0 ? IDX(cx, cy, 0) : (t == 1 ? IDX(cx, cy, 1) : IDX(cx, cy, -1));
-        g[i] = fma_r(wgt<R>(i), feq + fh, corr);
+        if constexpr (kind_srt(KIND)) {
+            const R om = c.omega;
+            g[i] = fma_r(wgt<R>(i), fma_r(om, feq, (R(2) - om) * fh), (R(1) - om) * g[i]);
+        } else {
+            R corr = R(0);
+            const int shell = cx * cx + cy * cy + czr * czr;
+            if (shell == 1) corr = cx != 0 ? f7 : (cy != 0 ? f8 : f9);
+            if (shell == 2) {
+                if (czr == 0) corr = (cx * cy > 0 ? R(0.25) : R(-0.25)) * c.c4;
+                else if (cy == 0) corr = (cx * czr > 0 ? R(0.25) : R(-0.25)) * c.c5;
+                else corr = (cy * czr > 0 ? R(0.25) : R(-0.25)) * c.c6;
+            }
+            g[i] = fma_r(wgt<R>(i), feq + fh, corr);
+        }
     }
-    if constexpr (G + 1 < 9) group_post_collision<R, G + 1>(c, hr, f7, f8, f9, g);
+    if constexpr (G + 1 < 9) group_post_collision<R, KIND, G + 1>(c, hr, f7, f8, f9, usq15, ua, g);
 }
 
-template <typename R>
+template <typename R, int KIND = KIND_MRT6>
 __device__ __forceinline__ void post_collision_all(const CollideCtx<R> &c, R (&g)[27])
 {
     // face-link combinations of the relaxed stress moments 7 and 8
     const R f7 = (c.c7 + c.c8) * (R(1) / R(6));                   // +-x faces
     const R f8 = c.c8 * (R(1) / R(6)) - c.c7 * (R(1) / R(3));      // +-y faces
     const R f9 = c.c7 * (R(1) / R(6)) - c.c8 * (R(1) / R(3));      // +-z faces
-    group_post_collision<R>(c, R(0.5) * c.rho, f7, f8, f9, g);
+    // second-order equilibrium: -3/2 u.u and u.a
+    const R usq15 = R(-1.5) * (c.ux * c.ux + c.uy * c.uy + c.uz * c.uz);
+    const R ua = c.ux * c.ax + c.uy * c.ay + c.uz * c.az;
+    group_post_collision<R, KIND>(c, R(0.5) * c.rho, f7, f8, f9, usq15, ua, g);
 }
 
 // Equilibrium deviation f^eq_I(rho = 1 + dr, u) - w_I (used by the initialiser)
@@ -445,6 +489,12 @@ __device__ __forceinline__ R feq_dev(R dr, const Axis<R> &X, const Axis<R> &Y, c
     const R exy = dx + dy + dx * dy;
     const R pim1 = exy + dz * (R(1) + exy);
     return wgt<R>(I) * (dr * (R(1) + pim1) + pim1);
+}
+// the same for the second-order equilibrium at rho = 1 and u = (0, 0, uz)
+template <int I, typename R> __device__ __forceinline__ R feq2_dev_z(R uz)
+{
+    const R cu = R(CZ(I)) * uz;
+    return wgt<R>(I) * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uz * uz);
 }
 
 // ---------------------------------------------------------------- forcing
@@ -505,7 +555,7 @@ __device__ __forceinline__ void body_force(const Geom &g, int z, R sig, R px, R 
 
 // One node's collision at a(x, n): moments, equilibrium, forcing and the
 // relaxation, in place on the gathered deviations v.
-template <typename T>
+template <typename T, int KIND = KIND_MRT6>
 __device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type (&v)[27],
                                         typename RealOf<T>::type sig, const Shape<typename RealOf<T>::type> &sh, int z)
 {
@@ -515,7 +565,7 @@ __device__ __forceinline__ void collide(const Geom &g, typename RealOf<T>::type 
     const Moments<R> m = moments_of<R>(v);
     R ux, uy, uz;
     const CollideCtx<R> c = collide_setup<R>(m, ax, ay, az, omega_of<R>(g), ux, uy, uz);
-    post_collision_all<R>(c, v);
+    post_collision_all<R, KIND>(c, v);
 }
 
 // Workgroup -> tile.  Workgroups are dispatched round-robin over the 8 XCDs

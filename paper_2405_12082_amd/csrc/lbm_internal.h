@@ -29,6 +29,7 @@ struct Geom {
     const double *ztab64;    // [2][nz]
     const double *sigma64;   // [n_sigma]
     double omega64, accel_z64;
+    int kind;  // collision kind (CollisionKind): 0 the paper's MRT scheme, 1..3 comparison schemes
 };
 
 // tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe
@@ -96,6 +97,10 @@ struct RingArgs {
 // launchers (return the hipError_t of the launch)
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                        hipStream_t s);
+// the same for the comparison schemes (g.kind != 0; two-buffer pattern, FP32
+// or FP64 storage)
+hipError_t launch_step_kind(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
+                            hipStream_t s);
 // steps n and n+1 in one launch (two-buffer pattern, bounce-back wall, FP32
 // or FP16 storage): src holds the state of step n, dst receives step n+2
 hipError_t launch_step2(int storage, const Geom &g, const Tiles2 &t, const void *src, void *dst, int step_off,

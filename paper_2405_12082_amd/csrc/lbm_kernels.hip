@@ -14,83 +14,9 @@
 // here too.
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_step.h"
 
 namespace lbm {
-
-// ---------------------------------------------------------------- helpers
-struct TileCoord {
-    int b, zc, k, kb;
-};
-__device__ __forceinline__ TileCoord tile_coord(const Tiles &t, int tile, int block)
-{
-    TileCoord c;
-    c.kb = tile % t.nkb;
-    const int rest = tile / t.nkb;
-    c.zc = rest % t.nzc;
-    c.b = rest / t.nzc + t.b0;
-    c.k = c.kb * block + threadIdx.x;
-    return c;
-}
-__device__ __forceinline__ TileCoord decode_tile(const Tiles &t, int block)
-{
-    return tile_coord(t, xcd_tile(blockIdx.x, gridDim.x, t.xcd), block);
-}
-
-__device__ __forceinline__ void load_columns(const Geom &g, int k, int (&col)[9])
-{
-#pragma unroll
-    for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
-}
-
-
-// ---------------------------------------------------------------- step
-// LBM_WAVES_PER_EU (compile time) asks the compiler for a register budget
-// allowing that many waves per SIMD.
-#ifndef LBM_WAVES_PER_EU
-#define LBM_WAVES_PER_EU 0
-#endif
-#if LBM_WAVES_PER_EU > 0
-#define LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LBM_WAVES_PER_EU)))
-#else
-#define LBM_OCCUPANCY
-#endif
-
-// Step variants: the two-buffer pattern (read FORM_S from src, aligned store
-// into dst) and the in-place AA pattern (even n: read own slots, store
-// swapped -> FORM_W; odd n: gather FORM_W, push to the neighbours -> FORM_N).
-enum StepMode : int { STEP_AB = 0, STEP_AA_EVEN = 1, STEP_AA_ODD = 2 };
-
-// One tile of one time step (column k of the tile, its z planes): gather of
-// g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
-// For the AA modes src and dst are the same buffer.
-template <typename T, int MODE, bool WALL = false>
-__device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *src, T *dst,
-                                          long long n)
-{
-    const int k = tc.k;
-    const Pull<T, WALL> p = make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
-    using R = typename RealOf<T>::type;
-    const Shape<R> sh = shape_of<R>(g, tc.b, k);
-    const R sig = sigma_of<R>(g, n);
-    char *pout = reinterpret_cast<char *>(dst + (size_t)tc.b * g.pipe);
-    const unsigned rowb = (unsigned)g.P * sizeof(T);
-    const int z0 = tc.zc * t.zchunk;
-    const int z1 = min(z0 + t.zchunk, g.nz);
-    constexpr int FORM = MODE == STEP_AB ? FORM_S : (MODE == STEP_AA_EVEN ? FORM_N : FORM_W);
-    for (int z = z0; z < z1; ++z) {
-        const unsigned zo = (unsigned)z * rowb;
-        const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
-        typename RealOf<T>::type v[27];
-        gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
-        collide<T>(g, v, sig, sh, z);
-        if constexpr (MODE == STEP_AB)
-            store_all<T>(pout, p.pbytes, zo + p.own, v);
-        else if constexpr (MODE == STEP_AA_EVEN)
-            store_swapped<T>(pout, p.pbytes, zo + p.own, v);
-        else
-            store_push<T>(pout, p, zo, zmo, zpo, v);
-    }
-}
 
 // (the FP32/FP16 interpolated-wall variants ask for the bounce-back variant's 4 waves
 // per SIMD: without the hint it lands one register above that budget)
@@ -445,10 +371,12 @@ struct SrcDense {  // populations [27][nz][ny][nx] of one pipe (float)
     }
 };
 
-struct SrcEq {  // f^eq(1, (0, 0, u0(column))) - w, in FP64
+struct SrcEq {  // f^eq(1, (0, 0, u0(column))) - w, in FP64 (eq2: the second-order equilibrium)
     const double *u0;
+    int eq2;
     template <int D> __device__ double get(int col, int) const
     {
+        if (eq2) return feq2_dev_z<D, double>(u0[col]);
         const Axis<double> zero = axis_factors(0.0);
         return feq_dev<D, double>(0.0, zero, zero, axis_factors(u0[col]));
     }
@@ -509,7 +437,7 @@ __global__ __launch_bounds__(256) void k_init(const Geom g, const double *__rest
     const int z = (int)(r % g.nz), b = (int)(r / g.nz);
     int col[9];
     load_columns(g, k, col);
-    write_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, SrcEq{u0}, k, z);
+    write_slots<T, FORM>(state + (size_t)b * g.pipe, g, col, SrcEq{u0, kind_eq2(g.kind) ? 1 : 0}, k, z);
 }
 
 template <typename T, int FORM>
@@ -693,6 +621,7 @@ int persistent_blocks_per_cu(int storage, int aa, int wall, int block)
 
 hipError_t launch_step(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off, hipStream_t s)
 {
+    if (g.kind != KIND_MRT6) return launch_step_kind(storage, g, t, src, dst, off, s);
     if (storage == 2) return step_t<double>(g, t, src, dst, off, s);
     return storage == 1 ? step_t<__half>(g, t, src, dst, off, s) : step_t<float>(g, t, src, dst, off, s);
 }

@@ -103,6 +103,13 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.init != 0 && c.init != 1) return bad("init must be 0 (rest) or 1 (log-law)");
     if (c.adjoint < 0 || c.adjoint > 2) return bad("adjoint must be 0 (none), 1 (FP32) or 2 (FP64)");
     if (c.init == 1 && (c.radius <= 0.0 || !(c.u_tau >= 0.0))) return bad("log-law init needs radius > 0, u_tau >= 0");
+    if (c.collision != 0 && c.collision != 1) return bad("collision must be 0 (MRT) or 1 (BGK)");
+    if (c.equilibrium != 0 && c.equilibrium != 1) return bad("equilibrium must be 0 (sixth order) or 1 (second order)");
+    if (c.collision != 0 || c.equilibrium != 0) {
+        if (c.storage == 1) return bad("the comparison schemes need FP32 or FP64 storage");
+        if (c.pattern != 0) return bad("the comparison schemes need the two-buffer pattern (pattern = 0)");
+        if (c.adjoint != 0) return bad("the comparison schemes have no adjoint (adjoint must be 0)");
+    }
     if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
         return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
     const int sidx = (c.storage >= 0 && c.storage <= 2) ? c.storage : 0;
@@ -297,7 +304,7 @@ struct lbm_ctx {
 
     int buf(long long n) const { return (int)((n + flip) & 1); }
     void *state(long long n) const { return ws + L.off_state[buf(n)]; }
-    bool can_fuse() const { return cfg.pattern == 0 && cfg.wall == 0 && cfg.storage != 2; }
+    bool can_fuse() const { return cfg.pattern == 0 && cfg.wall == 0 && cfg.storage != 2 && geom.kind == 0; }
     // form of the buffer that holds the state of step n
     int form(long long n) const { return cfg.pattern == 1 ? ((n & 1) ? FORM_W : FORM_N) : FORM_S; }
 };
@@ -401,6 +408,7 @@ struct PersistentPlan {
 };
 int persistent_plan(lbm_ctx *c, PersistentPlan &pl)
 {
+    if (c->geom.kind != 0) return fail(c, LBM_EINVAL, "persistent launches run the paper's collision only");
     int dev = 0, cus = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -623,6 +631,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     G.fshape64 = g.storage == 2 ? (const double *)(ws + L.off_fshape64) : nullptr;
     G.ztab64 = g.storage == 2 ? (const double *)(ws + L.off_ztab64) : nullptr;
     G.sigma64 = g.storage == 2 ? (const double *)(ws + L.off_sigma64) : nullptr;
+    G.kind = 2 * g.collision + g.equilibrium;
 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
@@ -785,8 +794,8 @@ int lbm_set_fused(lbm_ctx *c, int32_t steps_per_launch, int32_t zchunk, int32_t 
     CHECK_CTX(c);
     if (steps_per_launch < 0 || steps_per_launch > 2) return fail(c, LBM_EINVAL, "steps_per_launch must be 0, 1 or 2");
     if (steps_per_launch == 2 && !c->can_fuse())
-        return fail(c, LBM_EINVAL, "two steps per launch need the two-buffer pattern, the halfway bounce-back wall "
-                                   "and FP32 or FP16 storage");
+        return fail(c, LBM_EINVAL, "two steps per launch need the two-buffer pattern, the halfway bounce-back wall, "
+                                   "FP32 or FP16 storage and the paper's collision");
     if (zchunk < 0 || zchunk > 1024) return fail(c, LBM_EINVAL, "zchunk must be in 0..1024");
     if (xcd_remap < -1 || xcd_remap > 4096) return fail(c, LBM_EINVAL, "xcd_remap must be in -1..4096");
     if (steps_per_launch) c->fuse = steps_per_launch;
