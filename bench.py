@@ -229,10 +229,24 @@ def leg_turbulent_stats(steps=20000, stats_from=10000):
             "profiles_at": prof}
 
 
-def leg_batched(steps=200, graph_k=50):
-    """64 independent pipes 64x64x256 (R = 30) with their own seeded forcing:
-    one context, autotuned launch geometry and step order, graph replay;
-    against the same pipes run one after another as single-pipe contexts."""
+def _timed_steps(stream, fn, steps):
+    """ms per step of fn(steps) between HIP events on ``stream``."""
+    a, b = _events(stream)
+    a.record(stream)
+    fn(steps)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def leg_batched(steps=5000, graph_k=50, persistent_steps=1000):
+    """64 independent pipes 64x64x256 (R = 30) with their own seeded forcing,
+    5000 steps: one context, autotuned buffer pattern, launch geometry, step
+    order and launch form (graph replay of ordinary launches, or of one
+    persistent launch); against the same pipes run one after another as
+    single-pipe contexts, each in its own autotuned pattern and launch
+    geometry as graph replays (so the ratio isolates the batching).  The
+    persistent forms are also timed on their own (over 1000 steps)."""
     import torch
     import lbm_inputs as LI
     import paper_2405_12082_amd as P
@@ -242,71 +256,68 @@ def leg_batched(steps=200, graph_k=50):
     B = cfg["batch"]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        # launch geometry and buffer pattern (two buffers / AA in place)
-        tune = autotune.choose_pattern(cfg, amps, steps=10, stream=stream)
+        tune = autotune.choose_pattern(cfg, amps, steps=10, stream=stream, persistent=True)
         p = P.Pipe(dict(cfg, pattern=tune["pattern"]), amps, stream=stream)
         p.set_launch(**tune["best"])
-        p.step_graph(2 * graph_k, graph_k)  # capture + warm
-        a, b = _events(stream)
-        a.record(stream)
-        p.step_graph(steps, graph_k)
-        b.record(stream)
-        b.synchronize()
-        ms_batched = a.elapsed_time(b) / steps
-        # the same steps as one persistent cooperative launch (grid barrier per step)
-        p.step_persistent(2)
-        a, b = _events(stream)
-        a.record(stream)
-        p.step_persistent(steps)
-        b.record(stream)
-        b.synchronize()
-        ms_persistent = a.elapsed_time(b) / steps
-        # replays of a graph holding one persistent launch of graph_k steps
-        p.step_persistent_graph(2 * graph_k, graph_k)  # capture + warm
-        a, b = _events(stream)
-        a.record(stream)
-        p.step_persistent_graph(steps, graph_k)
-        b.record(stream)
-        b.synchronize()
-        ms_pgraph = a.elapsed_time(b) / steps
+        run = p.step_graph if tune["mode"] == "graph" else p.step_persistent_graph
+        run(2 * graph_k, graph_k)  # capture + warm
+        ms_batched = _timed_steps(stream, lambda n: run(n, graph_k), steps)
         nf = p.n_fluid
         ok = bool((p.diagnostics()[:, 4] == 0).all())
         del p
         torch.cuda.empty_cache()
-        # sequential single-pipe launches (eager, default geometry)
+        # the persistent forms in the persistent tuner's pattern and geometry
+        pt = tune["persistent"]
+        q = P.Pipe(dict(cfg, pattern=pt["pattern"]), amps, stream=stream)
+        q.set_launch(**pt["best"])
+        q.step_persistent(2)
+        ms_persistent = _timed_steps(stream, q.step_persistent, persistent_steps)
+        q.step_persistent_graph(2 * graph_k, graph_k)
+        ms_pgraph = _timed_steps(stream, lambda n: q.step_persistent_graph(n, graph_k), persistent_steps)
+        del q
+        torch.cuda.empty_cache()
+        # sequential single pipes, each tuned and run as graph replays
         c1 = dict(cfg, batch=1)
-        singles = [P.Pipe(c1, amps[i:i + 1], stream=stream) for i in range(B)]
+        t1 = autotune.choose_pattern(c1, amps[:1], steps=10, stream=stream)
+        singles = [P.Pipe(dict(c1, pattern=t1["pattern"]), amps[i:i + 1], stream=stream) for i in range(B)]
         for q in singles:
-            q.step(2)
-        a, b = _events(stream)
-        a.record(stream)
-        for q in singles:
-            q.step(steps)
-        b.record(stream)
-        b.synchronize()
-        ms_seq = a.elapsed_time(b) / steps
+            q.set_launch(**t1["best"])
+            q.step_graph(2 * graph_k, graph_k)
+
+        def seq(n):
+            for q in singles:
+                q.step_graph(n, graph_k)
+        ms_seq = _timed_steps(stream, seq, steps)
         del singles
         torch.cuda.empty_cache()
-    return {"value": round(B * nf / (ms_batched * 1e-3) / 1e6, 1), "unit": "MLUPS (aggregate)",
+    agg = lambda ms: round(B * nf / (ms * 1e-3) / 1e6, 1)
+    return {"value": agg(ms_batched), "unit": "MLUPS (aggregate)", "steps": steps,
             "ms_per_step": round(ms_batched, 4), "pipes": B, "fluid_nodes_per_pipe": nf,
-            "launch": tune["best"], "pattern": ["two buffers", "AA"][tune["pattern"]],
+            "launch": tune["best"], "launch_form": tune["mode"], "pattern": ["two buffers", "AA"][tune["pattern"]],
             "autotune_ms_by_pattern": {["two buffers", "AA"][q]: round(v, 4) for q, v in tune["by_pattern"].items()},
+            "autotune_ms_by_form": {k: round(v, 4) for k, v in tune["by_mode"].items()},
             "graph_steps": graph_k, "autotune_cached": tune["cached"],
-            "sequential_single_pipes": {"value": round(B * nf / (ms_seq * 1e-3) / 1e6, 1),
-                                        "ms_per_step": round(ms_seq, 4)},
+            "sequential_single_pipes": {"value": agg(ms_seq), "ms_per_step": round(ms_seq, 4),
+                                        "pattern": ["two buffers", "AA"][t1["pattern"]], "launch": t1["best"],
+                                        "form": "graph replay, autotuned per pipe", "steps": steps},
             "speedup_vs_sequential": round(ms_seq / ms_batched, 3),
-            "persistent_launch": {"value": round(B * nf / (ms_persistent * 1e-3) / 1e6, 1),
-                                  "ms_per_step": round(ms_persistent, 4)},
-            "persistent_launch_graph": {"value": round(B * nf / (ms_pgraph * 1e-3) / 1e6, 1),
-                                        "ms_per_step": round(ms_pgraph, 4), "steps_per_launch": graph_k},
+            "persistent_launch": {"value": agg(ms_persistent), "ms_per_step": round(ms_persistent, 4),
+                                  "pattern": ["two buffers", "AA"][pt["pattern"]], "launch": pt["best"],
+                                  "steps": persistent_steps},
+            "persistent_launch_graph": {"value": agg(ms_pgraph), "ms_per_step": round(ms_pgraph, 4),
+                                        "steps_per_launch": graph_k, "steps": persistent_steps},
             "state_finite": ok}
 
 
-def leg_adjoint():
+def leg_adjoint(fd_frac=1e-2):
     """Adjoint workload: 96x96x384 pipe (R = 45), 2000 steps, checkpoints
     every 100; gradient of the streamwise energy over steps 1501..2000 with
-    respect to the 12 trigger amplitudes.  Cost ratio = (recompute + adjoint
-    sweep) / plain forward over the same steps."""
+    respect to the 12 trigger amplitudes, by the FP32 forward with the
+    adjoint state in FP64 (the path that meets 1e-4 against central
+    differences) and in FP32 (faster, 1.4e-4).  Cost ratio = (recompute +
+    adjoint sweep) / plain forward over the same steps.  Accuracy: relative
+    L2 distance to central differences (step 1% of the largest amplitude) of
+    the FP64-storage forward."""
     import numpy as np
     import torch
     import lbm_inputs as LI
@@ -315,29 +326,126 @@ def leg_adjoint():
     cfg = LI.preset("adjoint")
     amps = LI.preset_amplitudes(cfg)
     N = cfg["obs_end"] - 1
+    b, e, C = cfg["obs_begin"], cfg["obs_end"], cfg["checkpoint_every"]
+    stream = torch.cuda.Stream()
+    out = {"steps": N, "checkpoint_every": C, "gradient_accumulation": "fp64"}
+    with torch.cuda.stream(stream):
+        p = P.Pipe(cfg, amps, stream=stream)
+        p.step(2)
+        ms_fwd = _timed_steps(stream, p.step, N) * N
+        nf = p.n_fluid
+        del p
+        grads = {}
+        for prec in ("fp64", "fp32"):
+            run = EnergyAdjoint(cfg, b, e, checkpoint_every=C, stream=stream, precision=prec)
+            run.gradient(amps)  # warm (allocations, first launches)
+            J, g = run.gradient(amps)
+            t = dict(run.timing)
+            grads[prec] = g[0]
+            out[f"adjoint_state_{prec}"] = {"backward_ms": round(t["backward_ms"], 2),
+                                            "forward_with_checkpoints_ms": round(t["forward_ms"], 2),
+                                            "cost_ratio": round(t["backward_ms"] / ms_fwd, 3), "J": float(J[0])}
+            del run
+            torch.cuda.empty_cache()
+        ref = EnergyAdjoint(dict(cfg, storage=2), b, e, checkpoint_every=C, stream=stream, precision="fp64")
+        eps = fd_frac * np.abs(amps).max()
+        fd = np.zeros_like(grads["fp64"])
+        for q in range(fd.size):
+            ap, am = amps.copy(), amps.copy()
+            ap[0, q] += eps
+            am[0, q] -= eps
+            fd[q] = (ref.objective(ap)[0] - ref.objective(am)[0]) / (2 * eps)
+        del ref
+        torch.cuda.empty_cache()
+    for prec, g in grads.items():
+        out[f"adjoint_state_{prec}"]["rel_err_vs_central_differences"] = float(np.linalg.norm(g - fd) /
+                                                                               np.linalg.norm(fd))
+    out.update({"forward_plain_ms": round(ms_fwd, 2), "fluid_nodes": nf, "adjoint_state": "fp64",
+                "adjoint_fwd_cost_ratio": out["adjoint_state_fp64"]["cost_ratio"],
+                "grad_norm": float(np.linalg.norm(grads["fp64"])),
+                "central_differences": {"forward": "fp64 storage", "step": f"{fd_frac:g} * max|amps|"}})
+    return out
+
+
+def leg_variants(steps=300):
+    """Comparison schemes (the BGK operator of Eq. (srt) and the second-order
+    equilibrium of the LBM-O(2) scheme, Section III) against the paper's
+    scheme: step rate on the turbulent pipe (FP32, 216 B per update for
+    every kind), and the A/B accuracy on a decaying shear wave u_x = 1e-4
+    sin(2 pi z / 64) at tau = 0.8 (FP64 storage): the fitted viscosity's
+    relative error, and its shift under a background velocity U_z = 0.1
+    (Galilean invariance: about -3 U^2 with the second-order equilibrium)."""
+    import numpy as np
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    names = {(0, 0): "mrt_o6 (paper)", (0, 1): "mrt_o2", (1, 0): "bgk_o6", (1, 1): "bgk_o2"}
+    out = {}
+    for (coll, eq), name in names.items():
+        r = leg_fp16(steps, storage=0) if (coll, eq) == (0, 0) else _leg_kind(steps, coll, eq)
+        N, tau, amp = 64, 0.8, 1e-4
+        nu = (tau - 0.5) / 3.0
+        kk = 2 * np.pi / N
+        T = int(1.0 / (nu * kk * kk))
+        z = np.arange(N)
+        fits = {}
+        for U0 in (0.0, 0.1):
+            c = dict(nx=1, ny=1, nz=N, batch=1, radius=0.0, tau=tau, accel_z=0.0, storage=2, init=0,
+                     collision=coll, equilibrium=eq)
+            p = P.Pipe(c)
+            g = _shear_wave_state(N, amp, U0, eq)
+            p.set_populations(torch.from_numpy(g[None]).cuda(), 0)
+            a = []
+            for n in (T // 4, T):
+                p.step(n)
+                ux = p.moments()[1].cpu().numpy()[0, 0, :, 0, 0].astype(np.float64)
+                a.append(abs(np.sum(ux * np.exp(-2j * np.pi * z / N))) * 2 / N)
+            fits[U0] = float(np.log(a[0] / a[1]) / (kk * kk * T) / nu - 1.0)
+            del p
+        out[name] = {"mlups": r["value"], "ms_per_step": r["ms_per_step"], "frac": r["frac"],
+                     "shear_wave_nu_rel_err": fits[0.0], "galilean_shift_U0.1": fits[0.1] - fits[0.0]}
+    return out
+
+
+def _leg_kind(steps, collision, equilibrium):
+    import torch
+    import lbm_inputs as LI
+    import paper_2405_12082_amd as P
+    cfg = dict(LI.preset("turbulent"), collision=collision, equilibrium=equilibrium)
+    amps = LI.preset_amplitudes(cfg)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         p = P.Pipe(cfg, amps, stream=stream)
-        a, b = _events(stream)
-        a.record(stream)
-        p.step(N)
-        b.record(stream)
-        b.synchronize()
-        ms_fwd = a.elapsed_time(b)
-        nf = p.n_fluid
+        p.step(20)
+        ms = _timed_steps(stream, p.step, steps)
+        nf, bpu = p.n_fluid, int(p.layout.bytes_per_update)
         del p
-        run = EnergyAdjoint(cfg, cfg["obs_begin"], cfg["obs_end"], checkpoint_every=cfg["checkpoint_every"],
-                            stream=stream, precision="fp32")
-        J, g = run.gradient(amps)
-        t = dict(run.timing)
-        del run
         torch.cuda.empty_cache()
-    return {"steps": N, "forward_plain_ms": round(ms_fwd, 2),
-            "forward_with_checkpoints_ms": round(t["forward_ms"], 2), "backward_ms": round(t["backward_ms"], 2),
-            "adjoint_fwd_cost_ratio": round(t["backward_ms"] / ms_fwd, 3),
-            "J": float(J[0]), "grad_norm": float(np.linalg.norm(g[0])), "adjoint_state": "fp32",
-            "gradient_accumulation": "fp64",
-            "fluid_nodes": nf, "checkpoint_every": cfg["checkpoint_every"]}
+    gbs = nf * bpu / (ms * 1e-3) / 1e9
+    return {"value": round(nf / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 4),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def _shear_wave_state(N, amp, U0, equilibrium):
+    """Deviations f^eq(1, (amp sin(2 pi z / N), 0, U0)) - w of a 1x1xN column
+    (sixth- or second-order equilibrium, the same expansion as the kernels'
+    initial states)."""
+    import numpy as np
+    c = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, 1, 0], [1, -1, 0], [-1, -1, 0], [1, 0, 1], [-1, 0, 1], [1, 0, -1], [-1, 0, -1],
+                  [0, 1, 1], [0, -1, 1], [0, 1, -1], [0, -1, -1], [1, 1, 1], [-1, 1, 1], [1, -1, 1], [-1, -1, 1],
+                  [1, 1, -1], [-1, 1, -1], [1, -1, -1], [-1, -1, -1]], float)
+    w = np.array([8 / 27 / 4 ** int(np.dot(ci, ci)) for ci in c])
+    g = np.zeros((27, N, 1, 1))
+    for k in range(N):
+        u = np.array([amp * np.sin(2 * np.pi * k / N), 0.0, U0])
+        if equilibrium:  # second order: w (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u)
+            cu = c @ u
+            feq = w * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * u @ u)
+        else:  # sixth order, product form: w prod_a (1 - 3/2 u_a^2 | 1 +- 3 u_a + 3 u_a^2)
+            feq = w * np.prod(np.where(c == 0, 1 - 1.5 * u ** 2, 1 + 3 * c * u + 3 * u ** 2), axis=1)
+        g[:, k, 0, 0] = feq - w
+    return g.astype(np.float32)
 
 
 def run_precision(steps=5000, sample_every=100, oracle_steps=100):
@@ -435,7 +543,8 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--xcd-remap", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fp16,aa,bouzidi,two_step,paper,batched,adjoint,precision,turbulent_stats",
+    ap.add_argument("--legs", default="fp16,aa,bouzidi,two_step,paper,batched,adjoint,variants,precision,"
+                                      "turbulent_stats",
                     help="extra measurements after the timed region (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -515,7 +624,7 @@ def main():
                 e = torch.cuda.Event(enable_timing=True)
                 e.record(stream)
                 seg_ev.append((s, e))
-            if s % 10 == 5:  # bracket every tenth step kernel with events
+            if args.steps < 100 or s % 10 == 5:  # bracket every step kernel of a short run, else every tenth
                 a = torch.cuda.Event(enable_timing=True)
                 b = torch.cuda.Event(enable_timing=True)
                 a.record(stream)
@@ -592,7 +701,7 @@ def main():
         extra[leg] = {"fp16": leg_fp16, "aa": leg_aa, "bouzidi": leg_bouzidi, "paper": leg_paper,
                       "two_step": leg_two_step,
                       "batched": leg_batched, "turbulent_stats": leg_turbulent_stats,
-                      "adjoint": leg_adjoint,
+                      "adjoint": leg_adjoint, "variants": leg_variants,
                       "precision": leg_precision}[leg]()
     if extra:
         out["extra"] = extra

@@ -45,6 +45,7 @@ class EnergyAdjoint:
         self.ckpt = None
         self.ring = None
         self.timing = {}
+        self.runs = 0  # forward runs so far: the checkpoints belong to the last one
 
     @property
     def last_step(self) -> int:
@@ -79,6 +80,7 @@ class EnergyAdjoint:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         J = self.objective(amps, keep_checkpoints=True)
+        self.runs += 1
         e1.record()
         torch.cuda.synchronize()
         self.timing = {"forward_ms": e0.elapsed_time(e1), "steps": self.last_step}
@@ -125,11 +127,15 @@ class PipeEnergy(torch.autograd.Function):
     def forward(ctx, amps: torch.Tensor, runner: EnergyAdjoint):
         J = runner.forward(amps.detach().cpu().numpy().astype(np.float64))
         ctx.runner = runner
+        ctx.run = runner.runs
         ctx.meta = (amps.dtype, amps.device)
         return torch.as_tensor(J, dtype=amps.dtype, device=amps.device)
 
     @staticmethod
     def backward(ctx, gJ):
         dtype, device = ctx.meta
+        if ctx.runner.runs != ctx.run:
+            raise RuntimeError("PipeEnergy: the runner ran another forward pass after this node; its checkpoints "
+                               "belong to that run (use one EnergyAdjoint per node)")
         g = torch.as_tensor(ctx.runner.backward(), dtype=dtype, device=device)
         return gJ.reshape(-1, 1) * g, None

@@ -8,7 +8,10 @@ does not advance the simulation.  Results are cached in a JSON file keyed by
 the pipe shape, batch, storage, buffer pattern and GPU architecture.
 :func:`choose_pattern` tunes the two-buffer and the AA pattern of a
 configuration and returns the faster (the pattern is fixed when a context is
-created, so it creates one context per pattern).
+created, so it creates one context per pattern); with ``persistent=True`` it
+also times replays of a graph holding one persistent launch of the same
+steps (``lbm_step_persistent_graph``) at each block size and z-chunk, and
+picks the faster launch form.
 """
 from __future__ import annotations
 
@@ -95,21 +98,66 @@ def autotune(pipe, steps: int = 10, cache_path: str | None = DEFAULT_CACHE, forc
     return dict(rec, cached=False)
 
 
+def _time_persistent(pipe, steps: int) -> float:
+    """ms per step of replays of a graph holding one persistent launch of
+    ``steps`` steps, after one replay that captures it."""
+    steps += steps % 2
+    stream = pipe.stream
+    pipe.step_persistent_graph(steps, steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pipe.step_persistent_graph(steps, steps)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_persistent(pipe, steps: int = 10) -> dict:
+    """Fastest (block, zchunk) of the persistent-launch graph form (the
+    co-resident workgroups own whole pipes, so pipes per launch, step order
+    and tile order do not apply); the state is restored afterwards."""
+    blob, step0 = pipe.save()
+    blob = blob.clone()
+    res = []
+    for block, zchunk in itertools.product((64, 128, 256, 512), (1, 2, 4)):
+        pipe.set_launch(block=block, zchunk=zchunk)
+        res.append((_time_persistent(pipe, steps), dict(block=block, zchunk=zchunk)))
+    pipe.load(blob, step0)
+    torch.cuda.synchronize()
+    ms, best = min(res, key=lambda r: r[0])
+    return {"best": best, "ms_per_step": ms, "tried": len(res)}
+
+
 def choose_pattern(cfg: dict, amps, steps: int = 10, cache_path: str | None = DEFAULT_CACHE, force: bool = False,
-                   device="cuda", stream=None) -> dict:
+                   device="cuda", stream=None, persistent: bool = False) -> dict:
     """Autotune the two-buffer (0) and the AA (1) pattern of ``cfg`` and
     return the faster: {"pattern", "best" (launch geometry), "ms_per_step",
-    "by_pattern": {pattern: ms_per_step}, "cached"}.  Configurations with
-    adjoint buffers allow only the two-buffer pattern."""
+    "by_pattern": {pattern: ms_per_step}, "mode" ("graph": replays of a graph
+    of ordinary launches; "persistent_graph": replays of a graph holding one
+    persistent launch), "by_mode", "cached"}.  Configurations with adjoint
+    buffers allow only the two-buffer pattern; the persistent form is timed
+    only when ``persistent`` is set (its result is not cached)."""
     from .pipe import Pipe
     patterns = (0,) if cfg.get("adjoint", 0) else (0, 1)
-    res = {}
+    res, pers = {}, {}
     for pat in patterns:
         p = Pipe(dict(cfg, pattern=pat), amps, device=device, stream=stream)
         res[pat] = autotune(p, steps, cache_path, force)
+        if persistent:
+            pers[pat] = tune_persistent(p, steps)
         del p
         torch.cuda.empty_cache()
     pat = min(res, key=lambda q: res[q]["ms_per_step"])
-    return {"pattern": pat, "best": res[pat]["best"], "ms_per_step": res[pat]["ms_per_step"],
-            "by_pattern": {q: res[q]["ms_per_step"] for q in res},
-            "cached": all(r["cached"] for r in res.values())}
+    out = {"pattern": pat, "best": res[pat]["best"], "ms_per_step": res[pat]["ms_per_step"],
+           "by_pattern": {q: res[q]["ms_per_step"] for q in res}, "mode": "graph",
+           "cached": all(r["cached"] for r in res.values())}
+    if persistent:
+        pp = min(pers, key=lambda q: pers[q]["ms_per_step"])
+        out["by_mode"] = {"graph": res[pat]["ms_per_step"], "persistent_graph": pers[pp]["ms_per_step"]}
+        out["persistent"] = {"pattern": pp, "best": pers[pp]["best"], "ms_per_step": pers[pp]["ms_per_step"],
+                             "by_pattern": {q: pers[q]["ms_per_step"] for q in pers}}
+        if pers[pp]["ms_per_step"] < out["ms_per_step"]:
+            out.update(pattern=pp, best=pers[pp]["best"], ms_per_step=pers[pp]["ms_per_step"],
+                       mode="persistent_graph")
+    return out

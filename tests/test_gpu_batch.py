@@ -164,3 +164,44 @@ def test_full_size_ensemble_in_the_bench_launch(P):
         assert torch.equal(rho[b], r1[0]) and torch.equal(u[b], u1[0]), b
         del one
     assert (ens.diagnostics()[:, 4] == 0).all()
+
+
+@pytest.mark.parametrize("mode", ["graph_aa", "graph_ab", "persistent_graph_aa", "persistent_graph_ab"])
+def test_batched_pipes_each_match_their_oracle(P, oracle_mod, mode):
+    """Three pipes with distinct seeded forcing and distinct random states,
+    two steps through the ensemble launches (AA or two buffers, one pipe per
+    launch in pipe-major order with XCD eighths as the bench's tuned
+    ensemble, as graph replay or as one persistent launch in a graph): each
+    pipe equals its own oracle pipe within the tolerance of two single steps,
+    128 * 2^-24 * (max|g_in| + max|g_out|)."""
+    O = oracle_mod
+    pattern = 1 if mode.endswith("_aa") else 0
+    cfg = dict(nx=21, ny=23, nz=13, batch=3, radius=9.6, tau=0.56, accel_z=3e-6, n_modes=6, kz=3.0,
+               kappa=0.5, l0_frac=0.2, l_frac=0.4, period=40.0, force_off_step=1000, storage=0, wall=0,
+               pattern=pattern, init=1, u_tau=0.01)
+    amps = LI.batch_amplitudes(17, 3, 6, cfg["u_tau"], cfg["period"]) * 40.0
+    o1 = O.Pipe(O.make_config(**cfg), amps[0])
+    mask = o1.fluid_mask()
+    _, w, _ = O.lattice()
+    g0 = np.stack([LI.random_deviations(300 + b, (cfg["nz"], cfg["ny"], cfg["nx"])) for b in range(3)])
+    g0[:, :, ~mask] = 0.0
+    p = P.Pipe(cfg, amps)
+    p.set_launch(block=128, zchunk=1, xcd_remap=1, pipes_per_launch=1, pipe_major=1)
+    p.set_populations(torch.from_numpy(g0).cuda(), step=10)
+    _log(f"batched vs oracle: {mode}")
+    if mode.startswith("graph"):
+        p.step_graph(2, 2)
+    else:
+        p.step_persistent_graph(2, 2)
+    g2 = p.populations().cpu().numpy().astype(np.float64)
+    for b in range(3):
+        o = O.Pipe(O.make_config(**cfg), amps[b])
+        f0 = g0[b].astype(np.float64) + w[:, None, None, None]
+        f0[:, ~mask] = 0.0
+        o.set_f(f0, 10)
+        o.step(2)
+        go = o.get_f() - w[:, None, None, None]
+        err = np.abs(g2[b][:, mask] - go[:, mask]).max()
+        tol = 128 * 2.0 ** -24 * (np.abs(g0[b]).max() + np.abs(go[:, mask]).max())
+        _log(f"  pipe {b}: error {err:.3e} (tolerance {tol:.3e})")
+        assert err <= tol, b
