@@ -329,6 +329,26 @@ int lbm_ring_sample(lbm_ctx *ctx, double r0, int32_t ntheta, float *ring);
 int lbm_ring_spectrum(lbm_ctx *ctx, const float *ring, int32_t ntheta, int32_t mmax, double *spec, double *mean,
                       int32_t *dominant);
 
+/* lbm_ring_spectrum without a context, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the same transform and plane average of ring
+ * samples of batch pipes of nz planes (ring: device [batch][nz][ntheta]
+ * float; spec, mean, dominant as in lbm_ring_spectrum), enqueued on stream
+ * (a hipStream_t, NULL: the default stream).  It allocates nothing: its
+ * only scratch, the twiddle table, is a library-owned device array of 4096
+ * points (64 KiB) per GPU, held until the process ends, whose address the
+ * library looks up once per device (at lbm_init, or at the first call on
+ * that device, which should then be made outside graph capture).  Every
+ * call rewrites the part of the table it uses; calls that overlap on one
+ * GPU share the table and race.  Twiddles are computed on the device, so
+ * results equal lbm_ring_spectrum's to FP64 rounding (the dominant mode
+ * exactly, barring ties within rounding).  Async.
+ * Errors: LBM_EINVAL for NULL ring/spec, batch or nz < 1, batch * nz >
+ * 2^31 - 1, ntheta outside 4..4096 (the scratch limit), mmax outside
+ * 1..ntheta/2, dominant without mean; LBM_EHIP for a HIP error. */
+int lbm_ring_spectrum_static(const float *ring, int32_t batch, int32_t nz, int32_t ntheta, int32_t mmax,
+                             double *spec, double *mean, int32_t *dominant, void *stream);
+
 /* Message of the last error on ctx ("" if none; a static message if ctx is NULL). */
 const char *lbm_last_error(const lbm_ctx *ctx);
 /* Release the context (not the caller's memory).  Synchronises its stream. */

@@ -101,6 +101,7 @@ def lib():
         "lbm_recompute": ([vp, vp, i64, i32, vp, C.c_size_t], C.c_int),
         "lbm_ring_sample": ([vp, C.c_double, i32, vp], C.c_int),
         "lbm_ring_spectrum": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
+        "lbm_ring_spectrum_static": ([vp, i32, i32, i32, i32, vp, vp, vp, vp], C.c_int),
         "lbm_last_error": ([vp], C.c_char_p),
         "lbm_destroy": ([vp], None),
     }

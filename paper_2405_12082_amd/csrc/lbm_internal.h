@@ -134,6 +134,9 @@ hipError_t launch_reduce_profile(const Geom &g, const Tiles &t, const double *pa
 hipError_t launch_fill(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_set_step(long long *step_dev, long long value, int add, hipStream_t s);
 hipError_t launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+// device address, on the current device, of the scratch array of the
+// context-free spectrum entry point (looked up once per device)
+hipError_t static_scratch(double **out);
 
 // adjoint
 struct AdjointArgs {

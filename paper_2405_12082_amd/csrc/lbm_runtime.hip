@@ -586,6 +586,8 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     };
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
+    double *scratch_dev = nullptr;  // set up the context-free entry point's scratch on this device
+    if (e == hipSuccess) e = static_scratch(&scratch_dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = h2d(L.off_nbr, nbr.data(), nbr.size() * sizeof(int));
     if (e == hipSuccess) e = h2d(L.off_box, L.box.data(), L.box.size() * sizeof(int));

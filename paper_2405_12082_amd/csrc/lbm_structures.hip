@@ -7,6 +7,9 @@
 // By the Wiener-Khinchin relation the transform of the circular correlation
 // of one plane is |U(m)|^2 / sum_j du_j^2, U the DFT of the fluctuation du
 // (about the ring mean), so a plane costs one DFT of its N ring samples.
+#include <mutex>
+
+#include "../../include/lbm.h"
 #include "lbm_device.h"
 #include "lbm_internal.h"
 
@@ -177,4 +180,68 @@ hipError_t launch_spectrum_mean(const double *spec, int B, int nz, int mmax, dou
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- context-free spectrum
+// lbm_ring_spectrum_static: the transform above without a context or
+// workspace, for callers that cannot allocate device memory.  Its only
+// scratch is the twiddle table, in a file-scope device array of
+// kStaticRing points (64 KiB, one copy per GPU, held until the process
+// ends); the host never names the array directly: hipGetSymbolAddress
+// gives its address on each device once, at lbm_init or at the first call
+// on that device (with that device current), and that address is what the
+// kernels receive.  Every call rewrites the whole table it uses, so nothing
+// has to start at zero; calls that overlap on one GPU share the table and
+// race.
+constexpr int kStaticRing = 4096;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[2 * kStaticRing];
+
+// twiddles exp(-2 pi i q / n), q < n
+__global__ __launch_bounds__(256) void k_twiddle(double *__restrict__ tw, int n)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    double sn, cs;
+    sincospi(2.0 * (double)q / (double)n, &sn, &cs);
+    tw[2 * q] = cs;
+    tw[2 * q + 1] = -sn;
+}
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+hipError_t static_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace lbm
+
+extern "C" int lbm_ring_spectrum_static(const float *ring, int32_t batch, int32_t nz, int32_t ntheta, int32_t mmax,
+                                        double *spec, double *mean, int32_t *dominant, void *stream)
+{
+    using namespace lbm;
+    if (!ring || !spec || batch < 1 || nz < 1 || (long long)batch * nz > 0x7fffffffLL || ntheta < 4 ||
+        ntheta > kStaticRing || mmax < 1 || mmax > ntheta / 2 || (dominant && !mean))
+        return LBM_EINVAL;
+    double *tw = nullptr;
+    if (static_scratch(&tw) != hipSuccess) return LBM_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_twiddle, dim3((unsigned)((ntheta + 255) / 256)), dim3(256), 0, s, tw, ntheta);
+    if (hipGetLastError() != hipSuccess) return LBM_EHIP;
+    if (launch_ring_spectrum(ring, batch * nz, ntheta, mmax, tw, spec, s) != hipSuccess) return LBM_EHIP;
+    if (mean && launch_spectrum_mean(spec, batch, nz, mmax, mean, dominant, s) != hipSuccess) return LBM_EHIP;
+    return LBM_OK;
+}
