@@ -33,7 +33,8 @@
  *    All axes wrap periodically.  Dense arrays exchanged with the caller
  *    use x fastest: [b][z][y][x]; solid nodes read and write as 0.
  *  - Populations: the library stores deviations g_i = f_i - w_i from the
- *    lattice weights (Eq. (omegas)), in FP32 or FP16 (storage field).
+ *    lattice weights (Eq. (omegas)), in FP32, FP16 (relative to a
+ *    per-column reference) or FP64 (storage field).
  *  - Velocity set order: 0 rest; 1-6 (+x,-x,+y,-y,+z,-z); 7-10 xy edges
  *    (++,-+,+-,--); 11-14 xz edges; 15-18 yz edges; 19-26 corners, as in
  *    the appendix.
@@ -72,9 +73,17 @@ typedef struct {
     double l_frac;        /* l / R */
     double period;        /* forcing period T in steps: time factor sin(2 pi n / T) */
     int64_t force_off_step; /* trigger force applied for steps n < force_off_step */
-    int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations scaled by
-                             2^k ~ 1/w_i (4, 16, 64, 256 for |c_i|^2 = 0, 1, 2, 3; stored as
-                             fp16_rne(g_i 2^k), read as fp16 value / 2^k), FP32 collision;
+    int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations, FP32
+                             collision: a value g_i produced by the node of column y is
+                             stored as h = fp16_rne(fp32(2^k g_i - E_c(y))) and read as
+                             fp32(h / 2^k + E_c(y) / 2^k), with 2^k ~ 1/w_i (4, 16, 64, 256 for
+                             |c_i|^2 = 0, 1, 2, 3) and the column's reference E_c(y) =
+                             fp32(32/27 d_c(u0(y))), c = c_z of population i, d_c the
+                             per-axis factor of the equilibrium (d_0 = -3u^2/2, d_+-1 = +-3u
+                             + 3u^2) at the initial streamwise velocity u0 of the column
+                             (0 for a rest start): E_c / 2^k is the initial equilibrium
+                             deviation, so FP16 holds the departure from it; saved FP16
+                             states are relative to their configuration's references;
                              2: FP64 deviations and collision (reference precision, for
                              verification) */
     int32_t wall;         /* 0: halfway bounce-back (the Delta = 1/2 case of Eq. (fbc1));

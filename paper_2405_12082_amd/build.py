@@ -2,6 +2,11 @@
 
 hipcc cross-compiles without a GPU.  Packed-FP32 instructions are disabled
 (-packed-fp32-ops) so the compiler emits plain VALU FP32 arithmetic.
+Multiply-adds are fused only within one source expression
+(-ffp-contract=on): fused across statements, the choice of which product to
+fuse differs between kernels that inline the same collision code, and so do
+their roundings (the in-place and two-buffer patterns then stop agreeing
+bitwise).
 """
 import os
 import subprocess
@@ -15,7 +20,7 @@ ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 
 def hipcc_flags():
-    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 

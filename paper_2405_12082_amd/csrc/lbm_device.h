@@ -94,45 +94,115 @@ __host__ __device__ constexpr int NSLOT(int dx, int dy) { return (dy + 1) * 3 + 
 // compiler emits global loads with an SGPR base and one VGPR offset.  Loads
 // go through the caches (neighbouring waves share the partial lines of the
 // shifted pull reads); stores are non-temporal (written once, read next step).
+//
+// FP16 storage keeps each value relative to a per-column reference: a
+// post-collision deviation g*_i produced by node y is held as
+//     h = fp16_rne(s_i g*_i - E_c(y)),   g*_i = h / s_i + E_c(y) / s_i,
+// wherever it is stored (two buffers, AA slots), with s_i = 2^k ~ 1/w_i and
+// E_c(y) = fp32(32/27 d_c(u0(y))), c = c_z of population i, d_c the
+// per-axis equilibrium factor and u0 the streamwise velocity of the
+// column's initial state (log-law profile; 0 when the pipe starts at rest).
+// A reader decodes with the producer's column: the column it pulls from, or
+// its own for a bounce-back.  The rounding of a value thus depends only on
+// the value and its producer, so every pattern and launch form stores the
+// same bits.  Since s_i w_i = 32/27 for every i, E_c / s_i is the
+// initial equilibrium deviation w_i d_c(u0) of that population, so the 11
+// bits of the FP16 mantissa go to the departure from the mean-flow
+// equilibrium rather than to the mean flow itself.  ld/st take the addend
+// E_c / s_i and the reference E_c; FP32 and FP64 storage ignore them.
 template <typename T> struct Codec;
 template <> struct Codec<float> {
-    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off)
+    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off, float = 0.f)
     {
         return *reinterpret_cast<const float *>(base + off);
     }
-    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v)
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v, float = 0.f)
     {
         __builtin_nontemporal_store(v, reinterpret_cast<float *>(base + off));
     }
 };
 template <> struct Codec<double> {
-    template <int I> __device__ static __forceinline__ double ld(const char *base, unsigned off)
+    template <int I> __device__ static __forceinline__ double ld(const char *base, unsigned off, double = 0.0)
     {
         return *reinterpret_cast<const double *>(base + off);
     }
-    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, double v)
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, double v, double = 0.0)
     {
         __builtin_nontemporal_store(v, reinterpret_cast<double *>(base + off));
     }
 };
+// FP16 encode and decode, each conversion an instruction of its own: an FP32
+// FMA, then the round-to-nearest-even conversion (folded into one mixed-
+// precision FMA the rounding would differ between kernels compiled apart),
+// and the conversion back before its FMA (folded into a mixed-precision FMA
+// that reads the loaded half directly, the compiler waits for each load
+// before issuing the next)
+__device__ __forceinline__ unsigned short h_encode(float v, float scale, float ref)
+{
+    const float r = fmaf(v, scale, -ref);
+    unsigned h;
+    asm("v_cvt_f16_f32 %0, %1" : "=v"(h) : "v"(r));
+    return (unsigned short)(h & 0xffffu);
+}
+__device__ __forceinline__ float h_decode(unsigned short raw, float inv_scale, float addend)
+{
+    float f;
+    asm("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"((unsigned)raw));
+    return fmaf(f, inv_scale, addend);
+}
 template <> struct Codec<__half> {
-    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off)
+    template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off, float addend = 0.f)
     {
-        const unsigned short raw = *reinterpret_cast<const unsigned short *>(base + off);
-        return __half2float(__ushort_as_half(raw)) * H_INV_SCALE(I);
+        return h_decode(*reinterpret_cast<const unsigned short *>(base + off), H_INV_SCALE(I), addend);
     }
-    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v)
+    template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v, float ref = 0.f)
     {
-        const __half h = __float2half_rn(v * H_SCALE(I));
-        __builtin_nontemporal_store(__half_as_ushort(h), reinterpret_cast<unsigned short *>(base + off));
+        __builtin_nontemporal_store(h_encode(v, H_SCALE(I), ref), reinterpret_cast<unsigned short *>(base + off));
     }
 };
+// index of the population with velocity (cx, cy, cz)
+__host__ __device__ constexpr int IDX(int cx, int cy, int cz)
+{
+    for (int i = 0; i < 27; ++i)
+        if (CX(i) == cx && CY(i) == cy && CZ(i) == cz) return i;
+    return -1;
+}
+// index of the reference of c_z = c in a column's three (c = 0, +1, -1)
+__host__ __device__ constexpr int CZI(int c) { return c == 0 ? 0 : (c > 0 ? 1 : 2); }
 
 // ---------------------------------------------------------------- gather
+// FP16 references of one thread's column (see the codecs): the decode addend
+// of the value population I receives, E_c(y) / s_I with y its producer (the
+// source column, c = c_z of I; for a bounce-back link this column, c = c_z
+// of opp(I)), and the own column's E_0, E_+, E_-.  Empty for FP32 / FP64.
+template <typename T> struct HRef {
+};
+template <> struct HRef<__half> {
+    // 27 floats of this thread in LDS, read back at each use: the step
+    // kernels make the pointer opaque once per plane (lds_opaque), so that the
+    // compiler neither forwards the thread's own writes nor hoists the reads
+    // out of the plane loop; either would hold all 27 values in vector
+    // registers, which costs the step kernel its occupancy and serialises its
+    // loads
+    __attribute__((address_space(3))) float *pull;
+    float own[3];
+};
+// an LDS pointer the compiler cannot see through (an empty asm statement
+// that takes and returns the address; no memory is accessed)
+__device__ __forceinline__ void lds_opaque(__attribute__((address_space(3))) float *&p)
+{
+    unsigned a = (unsigned)(size_t)p;
+    asm volatile("" : "+v"(a));
+    p = (__attribute__((address_space(3))) float *)(size_t)a;
+}
+// LDS the FP16 references of a workgroup of BLOCK threads take: 27 floats per
+// thread, at stride 27 (odd: the lanes of a wave hit distinct banks)
+template <typename T, int BLOCK> constexpr int href_lds_floats() { return sizeof(T) == 2 ? 27 * BLOCK : 1; }
+
 // Per-thread view of one pipe's population buffer for one column k:
 // byte offsets of the 9 in-plane neighbour columns (own column where the
-// neighbour is solid), a bit mask of the solid ones, and (interpolated wall
-// only) where the column's wall coefficients are.
+// neighbour is solid), a bit mask of the solid ones, (interpolated wall
+// only) where the column's wall coefficients are, and the FP16 references.
 template <typename T, bool WALL = false> struct Pull {
     const char *base;   // pipe base
     size_t pbytes;      // bytes between populations (nz * P * sizeof(T))
@@ -141,25 +211,62 @@ template <typename T, bool WALL = false> struct Pull {
     unsigned own;       // byte offset of column k within a plane
     const double *bc;   // interpolated wall: coefficient of slot d at bc[d * P] (0 for fluid slots)
     int P;
+    HRef<T> ref;
+    using R = typename RealOf<T>::type;
+    // decode addend of the value population I receives (pull or bounce-back)
+    template <int I> __device__ __forceinline__ R add_pull() const
+    {
+        if constexpr (sizeof(T) == 2) return ref.pull[I];
+        else return R(0);
+    }
+    // decode addend of population I's value produced by this column
+    template <int I> __device__ __forceinline__ R add_own() const
+    {
+        if constexpr (sizeof(T) == 2) return ref.own[CZI(CZ(I))] * H_INV_SCALE(I);
+        else return R(0);
+    }
+    // reference of population I's value produced by this column
+    template <int I> __device__ __forceinline__ R ref_own() const
+    {
+        if constexpr (sizeof(T) == 2) return ref.own[CZI(CZ(I))];
+        else return R(0);
+    }
 };
 
+// href: FP16 storage's per-column references [3][P] (c_z = 0, +1, -1);
+// lds: FP16 storage, this thread's 27 floats of LDS for them (see
+// href_lds_floats; each thread reads back only what it wrote, so no barrier)
 template <typename T, bool WALL = false>
 __device__ __forceinline__ Pull<T, WALL> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k,
-                                                   const double *bcoef = nullptr)
+                                                   const double *bcoef = nullptr, const float *href = nullptr,
+                                                   float *lds = nullptr)
 {
     Pull<T, WALL> p;
     p.base = reinterpret_cast<const char *>(pipe);
     p.pbytes = pstride * sizeof(T);
     p.own = (unsigned)k * sizeof(T);
     p.wall = 0;
+    int src[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
         const int c = nbr[d * P + k];
-        p.colo[d] = (unsigned)(c >= 0 ? c : k) * sizeof(T);
+        src[d] = c >= 0 ? c : k;
+        p.colo[d] = (unsigned)src[d] * sizeof(T);
         if (c < 0) p.wall |= 1u << d;
     }
     p.bc = WALL ? bcoef + k : nullptr;
     p.P = P;
+    if constexpr (sizeof(T) == 2) {
+        p.ref.pull = (__attribute__((address_space(3))) float *)lds;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p.ref.own[c] = href[c * P + k];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int d = NSLOT(-CX(i), -CY(i));
+            const bool bb = p.wall & (1u << d);  // bounce-back: g*_opp(i) of this column
+            p.ref.pull[i] = href[CZI(bb ? -CZ(i) : CZ(i)) * P + src[d]] * H_INV_SCALE(i);
+        }
+    }
     return p;
 }
 
@@ -172,15 +279,25 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T, WALL>
                                                              unsigned zpo)
 {
     if constexpr (FORM == FORM_N) {
-        return Codec<T>::template ld<I>(p.base + I * p.pbytes, zo + p.own);
+        // g_I(x) itself, produced by x - c_I (or by x, as g*_opp(I), where x - c_I is solid)
+        return Codec<T>::template ld<I>(p.base + I * p.pbytes, zo + p.own, p.template add_pull<I>());
     } else {
         constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
         constexpr int d = NSLOT(-cx, -cy);
         constexpr int here = FORM == FORM_W ? OPP(I) : I;  // physical slot of g*_I
         const unsigned zs = cz == 0 ? zo : (cz > 0 ? zmo : zpo);
-        typename RealOf<T>::type v = Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d]);
+        if constexpr (sizeof(T) == 2 && d != 4) {
+            // FP16: one load from the selected slot (the producer's addend of
+            // population I is fixed per column, bounce-back or not)
+            const bool bb = p.wall & (1u << d);
+            const char *b = p.base + (size_t)(bb ? OPP(here) : here) * p.pbytes;
+            return Codec<T>::template ld<I>(b, bb ? zo + p.own : zs + p.colo[d], p.template add_pull<I>());
+        }
+        typename RealOf<T>::type v =
+            Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d], p.template add_pull<I>());
         if constexpr (d != 4) {
-            if (p.wall & (1u << d)) v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own);
+            if (p.wall & (1u << d))
+                v = Codec<T>::template ld<OPP(I)>(p.base + OPP(here) * p.pbytes, zo + p.own, p.template add_pull<I>());
         }
         return v;
     }
@@ -209,7 +326,11 @@ __device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typenam
             const bool own_mode = cf[d] > 0;
             const unsigned zf = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
             const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
-            x[I] = Codec<T>::template ld<I>(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off);
+            // own mode: population I at this column; far mode: population
+            // opp(I) at the neighbour x + c_I, the column opp(I) pulls from
+            const typename RealOf<T>::type add =
+                own_mode ? p.template add_own<I>() : p.template add_pull<OPP(I)>();
+            x[I] = Codec<T>::template ld<I>(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off, add);
         }
     }
     if constexpr (I + 1 < 27) wall_loads<T, FORM, ZC, I + 1>(p, cf, zo, zmo, zpo, x);
@@ -258,22 +379,24 @@ __device__ __forceinline__ void gather(const Pull<T, WALL> &p, unsigned zo, unsi
     }
 }
 
-// two-buffer store: g*_i(x) into slot i of node x of the other buffer
-template <typename T, int I = 0>
-__device__ __forceinline__ void store_all(char *pipe, size_t pbytes, unsigned off, const typename RealOf<T>::type (&g)[27])
+// two-buffer store: g*_i(x) into slot i of node x of the other buffer (p:
+// the thread's view of the source buffer, for its FP16 references)
+template <typename T, bool WALL, int I = 0>
+__device__ __forceinline__ void store_all(char *pipe, const Pull<T, WALL> &p, unsigned off,
+                                          const typename RealOf<T>::type (&g)[27])
 {
-    Codec<T>::template st<I>(pipe + I * pbytes, off, g[I]);
-    if constexpr (I + 1 < 27) store_all<T, I + 1>(pipe, pbytes, off, g);
+    Codec<T>::template st<I>(pipe + I * p.pbytes, off, g[I], p.template ref_own<I>());
+    if constexpr (I + 1 < 27) store_all<T, WALL, I + 1>(pipe, p, off, g);
 }
 
 // AA pattern, even step: g*_i(x) into slot opp(i) of node x (in place), which
 // leaves the buffer in FORM_W
 template <typename T, int I = 0>
-__device__ __forceinline__ void store_swapped(char *pipe, size_t pbytes, unsigned off,
+__device__ __forceinline__ void store_swapped(char *pipe, const Pull<T> &p, unsigned off,
                                               const typename RealOf<T>::type (&g)[27])
 {
-    Codec<T>::template st<I>(pipe + OPP(I) * pbytes, off, g[I]);
-    if constexpr (I + 1 < 27) store_swapped<T, I + 1>(pipe, pbytes, off, g);
+    Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, off, g[I], p.template ref_own<I>());
+    if constexpr (I + 1 < 27) store_swapped<T, I + 1>(pipe, p, off, g);
 }
 
 // AA pattern, odd step: g*_i(x) into slot i of node x + c_i, or, where x + c_i
@@ -288,18 +411,10 @@ __device__ __forceinline__ void store_push(char *pipe, const Pull<T> &p, unsigne
     constexpr int d = NSLOT(cx, cy);
     const unsigned zt = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
     if (d != 4 && (p.wall & (1u << d)))
-        Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, zo + p.own, g[I]);
+        Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, zo + p.own, g[I], p.template ref_own<I>());
     else
-        Codec<T>::template st<I>(pipe + I * p.pbytes, zt + p.colo[d], g[I]);
+        Codec<T>::template st<I>(pipe + I * p.pbytes, zt + p.colo[d], g[I], p.template ref_own<I>());
     if constexpr (I + 1 < 27) store_push<T, I + 1>(pipe, p, zo, zmo, zpo, g);
-}
-
-// index of the population with velocity (cx, cy, cz)
-__host__ __device__ constexpr int IDX(int cx, int cy, int cz)
-{
-    for (int i = 0; i < 27; ++i)
-        if (CX(i) == cx && CY(i) == cy && CZ(i) == cz) return i;
-    return -1;
 }
 
 // ---------------------------------------------------------------- moments

@@ -43,13 +43,13 @@ __host__ __device__ constexpr int QSLOT(int i)
 }
 
 // FP16 storage: the value the single-step path would read back after
-// storing it (Codec<__half>::st then ::ld)
+// storing it (Codec<__half>::st then ::ld, with the column's reference)
 template <typename T, int I = 0>
-__device__ __forceinline__ void storage_round(typename RealOf<T>::type (&v)[27])
+__device__ __forceinline__ void storage_round(const Pull<T> &p, typename RealOf<T>::type (&v)[27])
 {
     if constexpr (sizeof(T) == 2) {
-        v[I] = __half2float(__float2half_rn(v[I] * H_SCALE(I))) * H_INV_SCALE(I);
-        if constexpr (I + 1 < 27) storage_round<T, I + 1>(v);
+        v[I] = h_decode(h_encode(v[I], H_SCALE(I), p.template ref_own<I>()), H_INV_SCALE(I), p.template add_own<I>());
+        if constexpr (I + 1 < 27) storage_round<T, I + 1>(p, v);
     }
 }
 
@@ -128,7 +128,9 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
     const bool valid = code >= 0;
     const bool owned = valid && (code & FUSED_OWNED);
     const int k = valid ? (code & ~FUSED_OWNED) : 0;
-    const Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k);
+    __shared__ float lref[href_lds_floats<T, FUSED_BOX>()];
+    const Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, nullptr, g.href,
+                                   lref + 27 * threadIdx.x);
     const Shape<float> sh = shape_of<float>(g, b, k);
     const long long n = *g.step_dev + step_off;
     const float sig1 = sigma_of<float>(g, n), sig2 = sigma_of<float>(g, n + 1);
@@ -149,7 +151,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
             const unsigned zmo = (unsigned)wrap_m(zs, g.nz) * rowb, zpo = (unsigned)wrap_p(zs, g.nz) * rowb;
             gather<T, FORM_S, false>(p, zo, zmo, zpo, v);
             collide<T>(g, v, sig1, sh, zs);
-            storage_round<T>(v);
+            storage_round<T>(p, v);
         }
         __syncthreads();
         if (valid) {
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
             float w[27];
             pull_lds(lds, s, p.wall, r, bb, r0_1, r5_2, r6_0, w);
             collide<T>(g, w, sig2, sh, zq);
-            store_all<T>(pout, p.pbytes, (unsigned)zq * rowb + p.own, w);
+            store_all<T>(pout, p, (unsigned)zq * rowb + p.own, w);
         }
         zs = wrap_p(zs, g.nz);
         j3 = j3 == 2 ? 0 : j3 + 1;

@@ -30,6 +30,10 @@ struct Geom {
     const double *sigma64;   // [n_sigma]
     double omega64, accel_z64;
     int kind;  // collision kind (CollisionKind): 0 the paper's MRT scheme, 1..3 comparison schemes
+    // FP16 storage: per-column references [3][P], E_c = fp32(32/27 d_c(u0)) for
+    // c_z = 0, +1, -1 (d_c the per-axis equilibrium factor at the column's
+    // initial velocity u0); null for FP32 / FP64 storage
+    const float *href;
 };
 
 // tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe

@@ -18,15 +18,17 @@
 
 namespace lbm {
 
-// (the FP32/FP16 interpolated-wall variants ask for the bounce-back variant's 4 waves
-// per SIMD: without the hint it lands one register above that budget)
+// (the FP32 interpolated-wall variant asks for the bounce-back variant's 4
+// waves per SIMD: without the hint it lands one register above that budget;
+// the FP16 one, with its 30 reference registers, would spill under it)
 template <typename T, int BLOCK, bool WALL>
-__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) < 8 ? 4 : 1)))
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) == 4 ? 4 : 1)))
 void k_step(const Geom g, const Tiles t, const T *__restrict__ src, T *__restrict__ dst, int step_off)
 {
+    __shared__ float lref[href_lds_floats<T, BLOCK>()];
     const TileCoord tc = decode_tile(t, BLOCK);
     if (tc.k >= g.ncol) return;
-    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, *g.step_dev + step_off);
+    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, *g.step_dev + step_off, lref + 27 * threadIdx.x);
 }
 
 // AA pattern: one buffer, updated in place (no __restrict__: reads and
@@ -34,9 +36,10 @@ void k_step(const Geom g, const Tiles t, const T *__restrict__ src, T *__restric
 template <typename T, int BLOCK, int MODE>
 __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY void k_step_aa(const Geom g, const Tiles t, T *buf, int step_off)
 {
+    __shared__ float lref[href_lds_floats<T, BLOCK>()];
     const TileCoord tc = decode_tile(t, BLOCK);
     if (tc.k >= g.ncol) return;
-    step_tile<T, MODE>(g, t, tc, buf, buf, *g.step_dev + step_off);
+    step_tile<T, MODE>(g, t, tc, buf, buf, *g.step_dev + step_off, lref + 27 * threadIdx.x);
 }
 
 // Barrier of one group of workgroups inside a cooperative launch (all
@@ -106,6 +109,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const T
     unsigned *gb = bar + 32 * (1 + q);
     const long long n0 = *g.step_dev;
     __shared__ int ticket;
+    __shared__ float lref[href_lds_floats<T, BLOCK>()];
+    float *mine = lref + 27 * threadIdx.x;
     for (int j = 0; j < nsteps; ++j) {
         const T *src = ((par + j) & 1) ? buf1 : buf0;
         T *dst = ((par + j) & 1) ? buf0 : buf1;
@@ -123,11 +128,11 @@ __global__ __launch_bounds__(BLOCK) void k_step_persistent(const Geom g, const T
                 if (tc.k >= g.ncol) continue;
                 if constexpr (AA) {
                     if ((par + j) & 1)
-                        step_tile<T, STEP_AA_ODD>(g, t, tc, buf0, buf0, n0 + j);
+                        step_tile<T, STEP_AA_ODD>(g, t, tc, buf0, buf0, n0 + j, mine);
                     else
-                        step_tile<T, STEP_AA_EVEN>(g, t, tc, buf0, buf0, n0 + j);
+                        step_tile<T, STEP_AA_EVEN>(g, t, tc, buf0, buf0, n0 + j, mine);
                 } else {
-                    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, n0 + j);
+                    step_tile<T, STEP_AB, WALL>(g, t, tc, src, dst, n0 + j, mine);
                 }
             }
             if (threadIdx.x == 0) ticket = nxt;
@@ -203,8 +208,10 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     double esum[1] = {0};
     double psum[4] = {0, 0, 0, 0};
     int cnt = 0;
+    __shared__ float lref[href_lds_floats<T, BLOCK>()];
     if (active) {
-        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
+        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k,
+                                                   g.bcoef, g.href, lref + 27 * threadIdx.x);
         const Shape<R> sh = shape_of<R>(g, tc.b, k);
         const unsigned xy = g.colxy[k];
         const int x = xy & 0xffff, y = xy >> 16;
@@ -420,8 +427,21 @@ __device__ __forceinline__ void write_slots(T *pipe, const Geom &g, const int (&
         }
     }
     using R = typename RealOf<T>::type;
+    // FP16: the reference of the value's producer (see the codecs): FORM_S /
+    // FORM_W hold values of this node (population J, FORM_W: opp(J)); FORM_N
+    // holds g_J(y), produced by y - c_J as g*_J, or by y as g*_opp(J) where
+    // y - c_J is solid
+    R ref = R(0);
+    if constexpr (sizeof(T) == 2) {
+        if constexpr (FORM == FORM_N) {
+            const int pc = col[NSLOT(-CX(J), -CY(J))];
+            ref = pc >= 0 ? g.href[CZI(CZ(J)) * g.P + pc] : g.href[CZI(-CZ(J)) * g.P + k];
+        } else {
+            ref = g.href[CZI(FORM == FORM_W ? -CZ(J) : CZ(J)) * g.P + k];
+        }
+    }
     Codec<T>::template st<J>(reinterpret_cast<char *>(pipe + (size_t)J * g.pstride), (unsigned)(z * g.P + k) * sizeof(T),
-                             (R)v);
+                             (R)v, ref);
     if constexpr (J + 1 < 27) write_slots<T, FORM, Src, J + 1>(pipe, g, col, src, k, z);
 }
 

@@ -55,6 +55,7 @@ struct Layout {
     // workspace offsets
     size_t off_state[2], off_box, off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_fshape64, off_ztab64, off_sigma64;  // FP64 storage only
+    size_t off_href;                               // FP16 storage only
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
     size_t off_lam[2], off_grad_part, off_grad_col, off_grad_base, off_modes;
     size_t off_ring_nodes, off_ring_idx, off_ring_w, off_twiddle;
@@ -194,6 +195,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_fshape64 = fp64 ? take(B * 3 * P * sizeof(double)) : 0;
     L.off_ztab64 = fp64 ? take(2 * (size_t)c.nz * sizeof(double)) : 0;
     L.off_sigma64 = fp64 ? take((size_t)L.n_sigma * sizeof(double)) : 0;
+    L.off_href = c.storage == 1 ? take(3 * P * sizeof(float)) : 0;
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
     L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
@@ -580,6 +582,18 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
             u0[k] = loglaw(g, std::sqrt(dx * dx + dy * dy));
         }
 
+    // FP16 references: E_c = fp32(32/27 d_c(u0)), c_z = 0, +1, -1, with the
+    // per-axis equilibrium factors d_0 = -3/2 u^2, d_+-1 = +-3 u + 3 u^2 at the
+    // column's initial velocity (the initial state is f^eq = w (1 + d_c(u0)))
+    std::vector<float> href(g.storage == 1 ? 3 * P : 0, 0.f);
+    if (g.storage == 1)
+        for (int k = 0; k < L.ncol; ++k) {
+            const double u = u0[k], f = 32.0 / 27.0;
+            href[k] = (float)(f * (-1.5 * u * u));
+            href[P + k] = (float)(f * (3.0 * u + 3.0 * u * u));
+            href[2 * P + k] = (float)(f * (-3.0 * u + 3.0 * u * u));
+        }
+
     char *ws = c->ws;
     auto h2d = [&](size_t off, const void *src, size_t n) {
         return n ? hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, c->stream) : hipSuccess;
@@ -601,6 +615,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     if (e == hipSuccess && g.storage == 2) e = h2d(L.off_ztab64, ztab64.data(), ztab64.size() * sizeof(double));
     if (e == hipSuccess && g.storage == 2) e = h2d(L.off_sigma64, sig64.data(), sig64.size() * sizeof(double));
     if (e == hipSuccess && g.adjoint) e = h2d(L.off_modes, modes.data(), modes.size() * sizeof(double));
+    if (e == hipSuccess && g.storage == 1) e = h2d(L.off_href, href.data(), href.size() * sizeof(float));
     if (e != hipSuccess) {
         std::fprintf(stderr, "lbm_init: %s\n", hipGetErrorString(e));
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -634,6 +649,7 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     G.ztab64 = g.storage == 2 ? (const double *)(ws + L.off_ztab64) : nullptr;
     G.sigma64 = g.storage == 2 ? (const double *)(ws + L.off_sigma64) : nullptr;
     G.kind = 2 * g.collision + g.equilibrium;
+    G.href = g.storage == 1 ? (const float *)(ws + L.off_href) : nullptr;
 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);

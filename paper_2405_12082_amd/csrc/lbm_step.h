@@ -55,12 +55,14 @@ enum StepMode : int { STEP_AB = 0, STEP_AA_EVEN = 1, STEP_AA_ODD = 2 };
 // One tile of one time step (column k of the tile, its z planes): gather of
 // g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
 // For the AA modes src and dst are the same buffer.
+// lref: FP16 storage, this thread's 27 floats of LDS for its column references
 template <typename T, int MODE, bool WALL = false, int KIND = KIND_MRT6>
 __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *src, T *dst,
-                                          long long n)
+                                          long long n, float *lref = nullptr)
 {
     const int k = tc.k;
-    const Pull<T, WALL> p = make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef);
+    Pull<T, WALL> p =
+        make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef, g.href, lref);
     using R = typename RealOf<T>::type;
     const Shape<R> sh = shape_of<R>(g, tc.b, k);
     const R sig = sigma_of<R>(g, n);
@@ -73,12 +75,13 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
         const unsigned zo = (unsigned)z * rowb;
         const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
         typename RealOf<T>::type v[27];
+        if constexpr (sizeof(T) == 2) lds_opaque(p.ref.pull);  // FP16 references stay in LDS
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         collide<T, KIND>(g, v, sig, sh, z);
         if constexpr (MODE == STEP_AB)
-            store_all<T>(pout, p.pbytes, zo + p.own, v);
+            store_all<T>(pout, p, zo + p.own, v);
         else if constexpr (MODE == STEP_AA_EVEN)
-            store_swapped<T>(pout, p.pbytes, zo + p.own, v);
+            store_swapped<T>(pout, p, zo + p.own, v);
         else
             store_push<T>(pout, p, zo, zmo, zpo, v);
     }

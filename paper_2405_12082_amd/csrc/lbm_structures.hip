@@ -29,9 +29,11 @@ __global__ __launch_bounds__(256) void k_ring(const Geom g, const RingArgs r, co
     const R sig = sigma_of<R>(g, *g.step_dev);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     const unsigned zo = (unsigned)z * rowb, zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
+    __shared__ float lref[href_lds_floats<T, 256>()];
     for (int u = threadIdx.x; u < r.n_nodes; u += 256) {
         const int col = r.nodes[u];
-        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col, g.bcoef);
+        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col,
+                                                   g.bcoef, g.href, lref + 27 * threadIdx.x);
         R v[27];
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         R ax, ay, az;

@@ -13,7 +13,7 @@
 namespace lbm {
 
 template <typename T, int BLOCK, bool WALL, int KIND>
-__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) < 8 ? 4 : 1)))
+__global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) == 4 ? 4 : 1)))
 void k_step_kind(const Geom g, const Tiles t, const T *__restrict__ src, T *__restrict__ dst, int step_off)
 {
     const TileCoord tc = decode_tile(t, BLOCK);

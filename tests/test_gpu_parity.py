@@ -236,6 +236,10 @@ def test_fp16_storage_forced_run(gpu, O):
 
 
 def test_fp16_storage_laminar(gpu, O):
+    """Laminar pipe in FP16 storage, 100 steps: velocity within 1e-3 of the
+    oracle (the stated FP16 accuracy: its deviations carry 11 significant
+    bits, and the laminar case, with deviations of ~1e-6 relative to the
+    weights, is its worst case)."""
     cfg = LI.preset("laminar")
     cfg["storage"] = 1
     p = gpu.Pipe(cfg)
@@ -246,7 +250,7 @@ def test_fp16_storage_laminar(gpu, O):
     _, u_o = o.moments()
     err = _vel_err(u_g[0], u_o, o.fluid_mask())
     _log(f"fp16 laminar velocity error {err:.3e}")
-    assert err < 2e-2
+    assert err < 1e-3
 
 
 # ------------------------------------------------------------------ batching, graphs, checkpoints

@@ -1,18 +1,32 @@
 """Precision of the storage forms against the FP64 reference, per result
 (needs an MI355X).  The 64x64x256 precision pipe (R = 30) runs 5000 steps in
-FP64 (reference, tied to the FP64 oracle at step 100), FP32 and FP16 storage;
-errors are relative max norms (velocity, mean and rms profiles over the
-second half) and absolute differences (skewness, flatness); the FP64 run's
-FP64 sums (mass, momentum, energy) meet the oracle's at rounding level.  The stated
-tolerances are a small margin above the measured errors; FP16 storage does
-not resolve the small fluctuations of this mostly laminar pipe, so only its
-velocity and mean profile are bounded."""
+FP64 (reference, tied to the FP64 oracle at step 100), FP32 and FP16 storage.
+Errors: relative max norms (velocity; mean and rms profiles over the second
+half, sampled every 100 steps) and absolute differences (skewness,
+flatness); the FP64 run's FP64 sums (mass, momentum, energy) meet the
+oracle's at rounding level.
+
+Stated accuracy, asserted below:
+ * velocity after 100 steps within the storage's own precision: 1e-5 for
+   FP32 (the velocity target of the laminar case), 1e-3 for FP16 (deviations
+   with 11 significant bits); at most linear growth after that (10x at 1000
+   steps: the FP32 drift is linear in the steps);
+ * the statistics, for both storage forms, at the resolution of a profile
+   figure: mean within 0.5%, rms within 2% of the profile's maximum,
+   skewness within 0.05 and flatness within 0.1 (absolute).
+FP16 meets them because it stores each value relative to its column's
+initial equilibrium (the codec in include/lbm.h); stored relative to the
+lattice weights alone it missed them by 10-50x (rms 23%, skewness 1.1,
+flatness 2.4)."""
 import sys
 
 import pytest
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+VELOCITY = {"fp32": (1e-5, 1e-4), "fp16": (1e-3, 1e-2)}
+STATISTICS = {"mean_profile": 5e-3, "rms_profile": 2e-2, "skewness_profile_abs": 0.05, "flatness_profile_abs": 0.1}
 
 
 def test_storage_precision_per_result(oracle_mod):
@@ -25,10 +39,10 @@ def test_storage_precision_per_result(oracle_mod):
     assert r["fp64_gpu_vs_oracle_velocity"]["step_100"] < 3e-7  # through the FP32 export
     sums = r["fp64_gpu_vs_oracle_sums"]  # FP64 throughout: rounding level
     assert sums["mass"] < 1e-12 and sums["momentum"] < 1e-10 and sums["energy"] < 1e-10
-    f32, f16 = r["fp32"], r["fp16"]
-    assert f32["velocity_step_100"] < 2e-5 and f32["velocity_step_1000"] < 2e-4
-    assert f32["mean_profile"] < 1e-3 and f32["rms_profile"] < 5e-3
-    assert f32["skewness_profile_abs"] < 2e-2 and f32["flatness_profile_abs"] < 5e-2
-    assert f16["velocity_step_100"] < 5e-3 and f16["velocity_step_1000"] < 5e-2
-    assert f16["mean_profile"] < 0.1
-    assert f32["state_finite"] and f16["state_finite"]
+    for name, (v100, v1000) in VELOCITY.items():
+        res = r[name]
+        assert res["state_finite"], name
+        assert res["velocity_step_100"] < v100, (name, res)
+        assert res["velocity_step_1000"] < v1000, (name, res)
+        for key, bound in STATISTICS.items():
+            assert res[key] < bound, (name, key, res)
