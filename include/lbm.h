@@ -241,6 +241,17 @@ int lbm_set_populations(lbm_ctx *ctx, const float *g, int64_t step);
  * the output) when any population is non-finite. */
 int lbm_diagnostics(lbm_ctx *ctx, double *host_out);
 
+/* Failure watchdog of lbm_diagnostics (a guard for long runs): with
+ * mass_rel_tol > 0, lbm_diagnostics also returns LBM_ENAN (after filling its
+ * output, with a message naming the pipe) when a pipe's mass differs from
+ * its reference mass by more than mass_rel_tol relative.  The reference is
+ * the mass at the first lbm_diagnostics call after this call, lbm_init,
+ * lbm_load or lbm_set_populations.  The halfway bounce-back conserves mass to
+ * rounding; the interpolated wall does not (its drift is a property of the
+ * scheme).  0 turns the check off (the default).  Host only.
+ * Errors: LBM_EINVAL for a negative or non-finite limit. */
+int lbm_set_watchdog(lbm_ctx *ctx, double mass_rel_tol);
+
 /* Add the current state's streamwise-velocity power sums to the per-column
  * FP64 accumulators: sum over z of u_z, u_z^2, u_z^3, u_z^4 and the count
  * (statistics of Eq. (urmsformula), pooled over z).  Async. */

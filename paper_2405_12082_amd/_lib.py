@@ -88,6 +88,7 @@ def lib():
         "lbm_populations": ([vp, fp], C.c_int),
         "lbm_set_populations": ([vp, fp, i64], C.c_int),
         "lbm_diagnostics": ([vp, dp], C.c_int),
+        "lbm_set_watchdog": ([vp, C.c_double], C.c_int),
         "lbm_profile_accumulate": ([vp], C.c_int),
         "lbm_profile_reset": ([vp], C.c_int),
         "lbm_profile_read": ([vp, dp], C.c_int),

@@ -303,6 +303,11 @@ struct lbm_ctx {
     std::vector<double> ring_w, twiddle;
     double ring_r0 = -1.0;
     int ring_n = 0, tw_n = 0;
+    // failure watchdog of lbm_diagnostics: relative mass-drift limit (0: off)
+    // and the reference masses (taken at the first diagnostics call after
+    // lbm_init, lbm_load, lbm_set_populations or lbm_set_watchdog)
+    double watch_tol = 0.0;
+    std::vector<double> mass_ref;
 
     int buf(long long n) const { return (int)((n + flip) & 1); }
     void *state(long long n) const { return ws + L.off_state[buf(n)]; }
@@ -874,6 +879,7 @@ int lbm_set_populations(lbm_ctx *c, const float *g, int64_t step)
     CHECK_CTX(c);
     if (!g || step < 0) return fail(c, LBM_EINVAL, "lbm_set_populations: NULL input or negative step");
     c->step = step;
+    c->mass_ref.clear();
     HIPCHK(c, launch_set_pops(c->cfg.storage, c->form(step), c->geom, g, c->state(step), c->stream));
     HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
     return LBM_OK;
@@ -895,6 +901,32 @@ int lbm_diagnostics(lbm_ctx *c, double *host_out)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int b = 0; b < c->cfg.batch; ++b)
         if (host_out[b * 5 + 4] != 0.0 || !std::isfinite(host_out[b * 5])) return fail(c, LBM_ENAN, "non-finite populations");
+    if (c->watch_tol > 0.0) {
+        if (c->mass_ref.empty()) {
+            c->mass_ref.resize(c->cfg.batch);
+            for (int b = 0; b < c->cfg.batch; ++b) c->mass_ref[b] = host_out[b * 5];
+        } else {
+            for (int b = 0; b < c->cfg.batch; ++b) {
+                const double drift = std::fabs(host_out[b * 5] - c->mass_ref[b]) / std::fabs(c->mass_ref[b]);
+                if (!(drift <= c->watch_tol)) {
+                    char buf[160];
+                    std::snprintf(buf, sizeof buf, "mass drift of pipe %d: %.3e relative (limit %.3e)", b, drift,
+                                  c->watch_tol);
+                    return fail(c, LBM_ENAN, buf);
+                }
+            }
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_set_watchdog(lbm_ctx *c, double mass_rel_tol)
+{
+    CHECK_CTX(c);
+    if (!(mass_rel_tol >= 0.0) || !std::isfinite(mass_rel_tol))
+        return fail(c, LBM_EINVAL, "lbm_set_watchdog: the limit must be finite and >= 0");
+    c->watch_tol = mass_rel_tol;
+    c->mass_ref.clear();
     return LBM_OK;
 }
 
@@ -1010,6 +1042,7 @@ int lbm_load(lbm_ctx *c, const void *src, int64_t step)
     CHECK_CTX(c);
     if (!src || step < 0) return fail(c, LBM_EINVAL, "lbm_load: NULL source or negative step");
     c->step = step;
+    c->mass_ref.clear();
     HIPCHK(c, hipMemcpyAsync(c->state(step), src, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
     return LBM_OK;

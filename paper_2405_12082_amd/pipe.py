@@ -145,6 +145,11 @@ class Pipe:
         self._check(rc, "lbm_diagnostics")
         return out
 
+    def set_watchdog(self, mass_rel_tol: float):
+        """Make diagnostics() fail (LBM_ENAN) when a pipe's mass drifts from its
+        reference (the next diagnostics call) by more than mass_rel_tol; 0: off."""
+        self._check(self.lib.lbm_set_watchdog(self._ctx, float(mass_rel_tol)), "lbm_set_watchdog")
+
     def energy(self) -> np.ndarray:
         out = np.zeros(self.cfg.batch)
         self._check(self.lib.lbm_energy(self._ctx, out.ctypes.data_as(C.POINTER(C.c_double))), "lbm_energy")
