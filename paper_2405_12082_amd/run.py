@@ -16,6 +16,15 @@ correlation on r = 0.78 R (Section II.C) is found on the GPU every that many
 steps; the series, its transition matrix, the Chapman-Kolmogorov test, the
 self mode correlation and Taylor lengths (Section III; the paper samples
 every 20 steps over the last 10 T^LET) go into the result.
+
+``--spinup-steps S --spinup-storage 1`` runs the first S steps in FP16
+storage (half the bytes per step) and hands the state to the main storage
+through the dense populations; ``--save PATH`` writes, at the end of the run,
+the state, its step, the statistics gathered so far (the host copy of the
+per-column power sums and their sample count) and the mode series to a
+NumPy archive, and ``--resume PATH`` continues a run from one (same preset,
+storage and sampling), so a long run can span several processes; the state
+continues bitwise.
 """
 from __future__ import annotations
 
@@ -27,9 +36,23 @@ import time
 import numpy as np
 
 
+def _series(dominant) -> np.ndarray:
+    """The first pipe's dominant modes: ints (resumed) and device tensors [batch]."""
+    return np.array([d if isinstance(d, int) else int(d[0].item()) for d in dominant], dtype=np.int64)
+
+
+def _save(path, p, samples, profile, dominant, spec_sum, spec_n):
+    """Archive of a run in progress (see the module notes)."""
+    blob, step = p.save()
+    np.savez(path, state=blob.cpu().numpy(), step=step, samples=samples, profile=profile,
+             dominant=_series(dominant), spec_sum=np.zeros(0) if spec_sum is None else spec_sum.cpu().numpy(),
+             spec_n=spec_n)
+
+
 def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: int = 10000,
         storage: int = 0, wall: int | None = None, log=print, modes_every: int = 0, modes_from: int = 0,
-        r0_frac: float = 0.78, ntheta: int = 1024, mmax: int = 10) -> dict:
+        r0_frac: float = 0.78, ntheta: int = 1024, mmax: int = 10, spinup_steps: int = 0,
+        spinup_storage: int | None = None, save: str | None = None, resume: str | None = None) -> dict:
     import math
 
     import torch
@@ -49,6 +72,7 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
         raise ValueError("modes_every must be an even number >= 2")
     # one graph length for the whole run: a divisor of every sampling interval
     chunk = math.gcd(every, modes_every) if modes_every else every
+    t0 = time.perf_counter()
     p = Pipe(cfg, amps)
     nf = p.n_fluid
     nu = (cfg["tau"] - 0.5) / 3.0
@@ -56,10 +80,44 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
     samples = 0
     r0 = r0_frac * cfg["radius"]
     ring = None
-    dominant, spec_sum = [], None
-    t0 = time.perf_counter()
-    last_t, last_n = t0, 0
+    dominant, spec_sum, spec_n = [], None, 0
+    prof_host = None  # statistics of earlier processes (resume)
     n = 0
+    if resume:
+        arc = np.load(resume)
+        blob = torch.from_numpy(arc["state"]).to(p.device)
+        if blob.numel() != p.state_bytes:
+            raise ValueError(f"{resume}: the state does not match this configuration")
+        n = int(arc["step"])
+        p.load(blob, n)
+        samples = int(arc["samples"])
+        prof_host = arc["profile"]
+        dominant = [int(v) for v in arc["dominant"]]
+        spec_n = int(arc["spec_n"])
+        spec_sum = torch.from_numpy(arc["spec_sum"]).to(p.device) if spec_n else None
+        del blob
+        log(json.dumps({"resumed": resume, "step": n, "samples": samples, "modes": len(dominant)}))
+    elif spinup_steps and spinup_storage is not None and spinup_storage != storage:
+        # the first steps in another storage, then the state through the dense populations
+        q = Pipe(dict(cfg, storage=spinup_storage), amps)
+        while n < spinup_steps:
+            k = min(chunk, spinup_steps - n)
+            q.step_graph(k, chunk) if k == chunk else q.step(k)
+            n += k
+            if n % progress == 0 or n == spinup_steps:
+                d = q.diagnostics()[0]
+                log(json.dumps({"spinup_step": n, "storage": spinup_storage,
+                                "elapsed_s": round(time.perf_counter() - t0, 1), "mass": d[0] / nf,
+                                "mean_uz": d[3] / d[0], "non_finite": int(d[4])}))
+                if d[4] != 0:
+                    raise FloatingPointError(f"non-finite populations at spin-up step {n}")
+        g = q.populations()
+        del q
+        torch.cuda.empty_cache()
+        p.set_populations(g, n)
+        del g
+        torch.cuda.empty_cache()
+    last_t, last_n = time.perf_counter(), n
     while n < steps:
         k = min(chunk, steps - n)
         if k == chunk:
@@ -73,8 +131,9 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
         if modes_every and n >= modes_from and n % modes_every == 0:
             ring = p.ring_sample(r0, ntheta, out=ring)
             _, mean, dom = p.ring_spectrum(ring, mmax)
-            dominant.append(dom)
-            spec_sum = mean if spec_sum is None else spec_sum + mean
+            dominant.append(dom)  # device tensors until the end of the run
+            spec_sum = mean[0] if spec_sum is None else spec_sum + mean[0]  # first pipe
+            spec_n += 1
         if n % progress == 0 or n == steps:
             d = p.diagnostics()[0]
             torch.cuda.synchronize()
@@ -87,18 +146,22 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
             last_t, last_n = now, n
             if d[4] != 0 or not np.isfinite(d[0]):
                 raise FloatingPointError(f"non-finite populations at step {n}")
-    prof = radial_profiles(p.profile_read()[0], cfg) if samples else None
+    acc = p.profile_read()
+    if prof_host is not None:
+        acc = acc + prof_host
+    if save:
+        _save(save, p, samples, acc, dominant, spec_sum, spec_n)
+    prof = radial_profiles(acc[0], cfg) if samples else None
     out = {"preset": preset, "steps": steps, "stats_from": stats_from, "every": every, "samples": samples,
            "storage": storage, "wall": cfg["wall"], "fluid_nodes": nf,
            "params": {k: cfg[k] for k in ("nx", "ny", "nz", "radius", "tau", "accel_z", "u_tau", "period",
                                           "force_off_step", "n_modes")},
            "amplitudes": np.asarray(amps).tolist(), "wall_time_s": round(time.perf_counter() - t0, 1)}
     if dominant:
-        series = torch.stack(dominant).cpu().numpy()[:, 0]  # first pipe
+        series = _series(dominant)
         out["modes"] = {
             "every": modes_every, "from": modes_from, "r0": r0, "ntheta": ntheta, "mmax": mmax,
-            "series": series.tolist(),
-            "mean_spectrum": (spec_sum[0] / len(dominant)).cpu().numpy().tolist()}
+            "series": series.tolist(), "mean_spectrum": (spec_sum.cpu().numpy() / spec_n).tolist()}
     if dominant and series.min() >= 1:  # 0: a ring without fluctuations
         u_conv = float(np.interp(r0, prof["r"], prof["mean"])) if prof is not None else float("nan")
         out["modes"].update({
@@ -134,13 +197,18 @@ def main(argv=None) -> int:
     ap.add_argument("--r0-frac", type=float, default=0.78)
     ap.add_argument("--ntheta", type=int, default=1024)
     ap.add_argument("--mmax", type=int, default=10)
+    ap.add_argument("--spinup-steps", type=int, default=0, help="first steps in --spinup-storage")
+    ap.add_argument("--spinup-storage", type=int, default=None, help="storage of the spin-up (1: FP16)")
+    ap.add_argument("--save", default=None, help="archive the run's state and statistics at its end (.npz)")
+    ap.add_argument("--resume", default=None, help="continue from an archive written by --save")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     stats_from = a.stats_from if a.stats_from is not None else a.steps // 2
     res = run(a.preset, a.steps, stats_from, a.every, a.progress, a.storage, a.wall,
               log=lambda s: print(s, flush=True), modes_every=a.modes_every,
               modes_from=a.modes_from if a.modes_from is not None else stats_from, r0_frac=a.r0_frac,
-              ntheta=a.ntheta, mmax=a.mmax)
+              ntheta=a.ntheta, mmax=a.mmax, spinup_steps=a.spinup_steps, spinup_storage=a.spinup_storage,
+              save=a.save, resume=a.resume)
     text = json.dumps(res)
     if a.out:
         with open(a.out, "w") as f:

@@ -68,3 +68,44 @@ def test_run_records_the_dominant_mode_series(P):
     assert m["series"] == ref
     if min(ref) >= 1:
         np.testing.assert_allclose(m["transition_matrix"], H.transition_matrix(ref, 10))
+
+
+def test_run_save_resume_continues_bitwise(P, tmp_path):
+    """400 steps in one process equal 200 steps, an archive, and 200 more
+    resumed from it: the state bitwise, the sample count and mode series
+    exactly, the statistics to FP64 rounding (the resumed run adds the
+    archived sums on the host)."""
+    from paper_2405_12082_amd import run
+    kw = dict(every=100, progress=200, log=lambda s: None, modes_every=20, modes_from=200, ntheta=256, mmax=10)
+    whole = run.run("precision_ref", 400, 100, save=str(tmp_path / "whole.npz"), **kw)
+    run.run("precision_ref", 200, 100, save=str(tmp_path / "half.npz"), **kw)
+    resumed = run.run("precision_ref", 400, 100, resume=str(tmp_path / "half.npz"),
+                      save=str(tmp_path / "resumed.npz"), **kw)
+    a, b = np.load(tmp_path / "whole.npz"), np.load(tmp_path / "resumed.npz")
+    assert int(a["step"]) == int(b["step"]) == 400
+    assert np.array_equal(a["state"], b["state"])
+    assert resumed["samples"] == whole["samples"] == 4
+    assert resumed["modes"]["series"] == whole["modes"]["series"]
+    np.testing.assert_allclose(b["profile"], a["profile"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(resumed["modes"]["mean_spectrum"], whole["modes"]["mean_spectrum"], rtol=1e-12)
+    for key in ("mean", "rms"):
+        np.testing.assert_allclose(resumed["profiles"][key], whole["profiles"][key], rtol=1e-10, atol=1e-15)
+
+
+def test_run_fp16_spinup_hands_over_the_state(P):
+    """An FP16 spin-up of 200 steps, then FP32: the handed-over state is the
+    FP16 run's (the first FP32 diagnostics equal the FP16 run's mass to FP32
+    rounding of the export) and the run stays finite with its mass kept."""
+    from paper_2405_12082_amd import run
+    lines = []
+    res = run.run("precision_ref", 400, 300, every=100, progress=100, log=lines.append,
+                  spinup_steps=200, spinup_storage=1)
+    import json
+    recs = [json.loads(s) for s in lines]
+    spin = [r for r in recs if "spinup_step" in r]
+    main = [r for r in recs if "step" in r]
+    assert [r["spinup_step"] for r in spin] == [100, 200]
+    assert [r["step"] for r in main] == [300, 400]
+    assert all(r["non_finite"] == 0 for r in recs)
+    assert abs(main[0]["mass"] - spin[-1]["mass"]) < 1e-6
+    assert res["samples"] == 2
