@@ -28,7 +28,7 @@ SAMPLE_EVERY = 100
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_device.h", "lbm_kernels.hip"):
+    for f in ("lbm_device.h", "lbm_step.h", "lbm_kernels.hip"):
         h.update(open(os.path.join(ROOT, "paper_2405_12082_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -45,6 +45,56 @@ def measured_traffic(workload, storage):
     if not e or e.get("source_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
+
+
+def _counter_kib(folder, kernel_prefix, counter):
+    """Mean per-dispatch value (KiB) of one counter over the dispatches of
+    the kernels whose name starts with kernel_prefix, from a rocprofv3
+    --pmc CSV folder (``<folder>/*counter_collection.csv``)."""
+    import csv
+    import glob
+    vals = []
+    for path in glob.glob(os.path.join(folder, "*counter_collection.csv")):
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] == counter and row["Kernel_Name"].startswith(kernel_prefix):
+                vals.append(float(row["Counter_Value"]))
+    if not vals:
+        raise ValueError(f"{folder}: no {counter} for {kernel_prefix}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def record_traffic(folder, workload, storage):
+    """HBM bytes per step-kernel launch from four rocprofv3 --pmc runs under
+    folder (fetch<S>/ and write<S>/: ``bench.py --profile-steps 10 --storage
+    S``; copyf/ and copyw/: ``bench.py --copy-calibration 2048``), each
+    counter scaled by what it reads for the plain 2 GiB copy; written into
+    profiles/step_kernel_hbm_traffic.json under the current kernel source
+    hash.  Host only."""
+    import lbm_inputs as LI
+    from paper_2405_12082_amd import _lib
+    copy_bytes = 2048 * (1 << 20)
+    cf, _ = _counter_kib(os.path.join(folder, "copyf"), "__amd_rocclr_copyBuffer", "FETCH_SIZE")
+    cw, _ = _counter_kib(os.path.join(folder, "copyw"), "__amd_rocclr_copyBuffer", "WRITE_SIZE")
+    fetch_scale, write_scale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    f, nd = _counter_kib(os.path.join(folder, f"fetch{storage}"), "void lbm::k_step<", "FETCH_SIZE")
+    w, _ = _counter_kib(os.path.join(folder, f"write{storage}"), "void lbm::k_step<", "WRITE_SIZE")
+    cfg = LI.preset(workload)
+    cfg["storage"] = storage
+    lay = _lib.describe(_lib.make_config(**cfg))
+    alg = float(lay.n_fluid_nodes) * 27 * (2 if storage == 1 else 8 if storage == 2 else 4)
+    read, written = f * 1024 * fetch_scale, w * 1024 * write_scale
+    path = os.path.join(ROOT, "profiles", "step_kernel_hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        rec = {}
+    rec[f"{workload}:{storage}"] = {
+        "algorithmic_read": alg, "algorithmic_write": alg, "bytes_per_launch": int(round(read + written)),
+        "dispatches": nd, "fetch_scale": fetch_scale, "read_bytes": int(round(read)), "source_hash": kernel_source_hash(),
+        "write_bytes": int(round(written)), "write_scale": write_scale}
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1, sort_keys=True)
+    return rec[f"{workload}:{storage}"]
 
 
 def _oracle_rate(cfg, amps, nz, seconds):
@@ -552,7 +602,13 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of this many MiB 10 times (plain copy kernel of known "
                          "size, to calibrate HBM byte counters) and exit")
+    ap.add_argument("--record-traffic", default=None, metavar="DIR",
+                    help="host only: write the HBM traffic record of --workload/--storage from the "
+                         "rocprofv3 counter folders under DIR, and exit")
     args = ap.parse_args()
+    if args.record_traffic:
+        print(json.dumps(record_traffic(args.record_traffic, args.workload, args.storage)))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the stepper runs one pipe per GPU); --gpus {args.gpus} "
               "is not supported", file=sys.stderr)

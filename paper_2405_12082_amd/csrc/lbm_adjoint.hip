@@ -157,7 +157,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
 #pragma unroll
     for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
     __shared__ float lref[href_lds_floats<T, BLOCK>()];
-    const Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
+    Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
                                                k, g.bcoef, g.href, lref + 27 * threadIdx.x);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     using W = typename RealOf<T>::type;  // the forward step's arithmetic type
@@ -172,6 +172,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     for (int z = z0; z < z1; ++z) {
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
         W v[27];
+        pull_opaque<true>(p);
         gather<T, FORM_S, WALL>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
         // the forward's z factors, for the projection of the sensitivities
         double cz, sz;

@@ -110,22 +110,36 @@ __host__ __device__ constexpr int NSLOT(int dx, int dy) { return (dy + 1) * 3 + 
 // bits of the FP16 mantissa go to the departure from the mean-flow
 // equilibrium rather than to the mean flow itself.  ld/st take the addend
 // E_c / s_i and the reference E_c; FP32 and FP64 storage ignore them.
+// raw/dec split ld into the load of the stored word and its decode, for
+// paths that issue several conditional loads before decoding any.
 template <typename T> struct Codec;
 template <> struct Codec<float> {
+    using Raw = float;
     template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off, float = 0.f)
     {
         return *reinterpret_cast<const float *>(base + off);
     }
+    __device__ static __forceinline__ Raw raw(const char *base, unsigned off)
+    {
+        return *reinterpret_cast<const float *>(base + off);
+    }
+    template <int I> __device__ static __forceinline__ float dec(Raw r, float = 0.f) { return r; }
     template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v, float = 0.f)
     {
         __builtin_nontemporal_store(v, reinterpret_cast<float *>(base + off));
     }
 };
 template <> struct Codec<double> {
+    using Raw = double;
     template <int I> __device__ static __forceinline__ double ld(const char *base, unsigned off, double = 0.0)
     {
         return *reinterpret_cast<const double *>(base + off);
     }
+    __device__ static __forceinline__ Raw raw(const char *base, unsigned off)
+    {
+        return *reinterpret_cast<const double *>(base + off);
+    }
+    template <int I> __device__ static __forceinline__ double dec(Raw r, double = 0.0) { return r; }
     template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, double v, double = 0.0)
     {
         __builtin_nontemporal_store(v, reinterpret_cast<double *>(base + off));
@@ -151,9 +165,20 @@ __device__ __forceinline__ float h_decode(unsigned short raw, float inv_scale, f
     return fmaf(f, inv_scale, addend);
 }
 template <> struct Codec<__half> {
+    // a stored half, zero-extended into a word of its own (two halves packed
+    // into one register would make each load wait for the other)
+    using Raw = unsigned;
     template <int I> __device__ static __forceinline__ float ld(const char *base, unsigned off, float addend = 0.f)
     {
         return h_decode(*reinterpret_cast<const unsigned short *>(base + off), H_INV_SCALE(I), addend);
+    }
+    __device__ static __forceinline__ Raw raw(const char *base, unsigned off)
+    {
+        return *reinterpret_cast<const unsigned short *>(base + off);
+    }
+    template <int I> __device__ static __forceinline__ float dec(Raw r, float addend = 0.f)
+    {
+        return h_decode((unsigned short)r, H_INV_SCALE(I), addend);
     }
     template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v, float ref = 0.f)
     {
@@ -178,8 +203,8 @@ __host__ __device__ constexpr int CZI(int c) { return c == 0 ? 0 : (c > 0 ? 1 : 
 template <typename T> struct HRef {
 };
 template <> struct HRef<__half> {
-    // 27 floats of this thread in LDS, read back at each use: the step
-    // kernels make the pointer opaque once per plane (lds_opaque), so that the
+    // 27 floats of this thread in LDS, read back at each use: the kernels
+    // make the pointer opaque once per plane (pull_opaque), so that the
     // compiler neither forwards the thread's own writes nor hoists the reads
     // out of the plane loop; either would hold all 27 values in vector
     // registers, which costs the step kernel its occupancy and serialises its
@@ -270,6 +295,24 @@ __device__ __forceinline__ Pull<T, WALL> make_pull(const T *pipe, size_t pstride
     return p;
 }
 
+// Once per plane, FP16 storage: the LDS pointer of the references (see
+// HRef) and, with MASK, the solid-slot mask made opaque.  The FP16 gather
+// selects, per lane, the population a load reads (the pull or its
+// bounce-back); with the mask visible the compiler hoists the 27 resulting
+// 64-bit addresses out of the plane loop and keeps them in vector registers
+// (some 50).  Where that costs an occupancy level (the interpolated wall,
+// the AA pattern's push step, the observers) recomputing them per plane is
+// faster; in the plain two-buffer step it is not (measured), so that one
+// keeps them.  No effect for FP32 / FP64 storage.
+template <bool MASK, typename T, bool WALL>
+__device__ __forceinline__ void pull_opaque(Pull<T, WALL> &p)
+{
+    if constexpr (sizeof(T) == 2) {
+        lds_opaque(p.ref.pull);
+        if constexpr (MASK) asm volatile("" : "+v"(p.wall));
+    }
+}
+
 // Pull streaming, Eq. (streaming): g_i(x, n) = g*_i(x - c_i, n-1) if x - c_i
 // is fluid, else the halfway bounce-back g*_opp(i)(x, n-1) (the Delta = 1/2
 // case of Eq. (fbc1)).  zo/zmo/zpo: byte offsets of planes z, z-1, z+1
@@ -310,17 +353,20 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T, WALL>
 // 2 Delta): X = g*_opp(i)(x + c_i); cf = 1: bounce-back (also stored for
 // fluid slots, where it leaves the value unchanged).  Deviations g = f - w
 // combine like f: the weights sum to 1 and w_i = w_opp(i).  The X loads of
-// a node are issued in groups (slots of the same shell share the FP16
-// scale), then combined, so a wave with wall columns waits once per group.
+// a node are issued in groups (one c_z each), then decoded and combined, so
+// a wave with wall columns waits once per group: the stored words are
+// loaded under the lane's condition and decoded outside it (a decode
+// inside the condition would wait for its own load).
 template <typename T, int FORM, int ZC, int I = 0>
 __device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typename RealOf<T>::type (&cf)[9],
-                                           unsigned zo, unsigned zmo, unsigned zpo, typename RealOf<T>::type (&x)[27])
+                                           unsigned zo, unsigned zmo, unsigned zpo, typename Codec<T>::Raw (&x)[27])
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
     constexpr int d = NSLOT(-cx, -cy);
     if constexpr (d != 4 && cz == ZC) {
         constexpr int here = FORM == FORM_W ? OPP(I) : I;
-        // only the lanes with a cut link load (fluid slots keep x = 0, c = 1)
+        // only the lanes with a cut link load (fluid slots keep the zero
+        // word: they combine with c = 1, which leaves the value as it is)
         x[I] = 0;
         if (p.wall & (1u << d)) {
             const bool own_mode = cf[d] > 0;
@@ -328,25 +374,26 @@ __device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typenam
             const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
             // own mode: population I at this column; far mode: population
             // opp(I) at the neighbour x + c_I, the column opp(I) pulls from
-            const typename RealOf<T>::type add =
-                own_mode ? p.template add_own<I>() : p.template add_pull<OPP(I)>();
-            x[I] = Codec<T>::template ld<I>(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off, add);
+            x[I] = Codec<T>::raw(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off);
         }
     }
     if constexpr (I + 1 < 27) wall_loads<T, FORM, ZC, I + 1>(p, cf, zo, zmo, zpo, x);
 }
 
 template <typename T, int ZC, int I = 0>
-__device__ __forceinline__ void wall_combine(const typename RealOf<T>::type (&cf)[9],
-                                             const typename RealOf<T>::type (&x)[27], typename RealOf<T>::type (&v)[27])
+__device__ __forceinline__ void wall_combine(const Pull<T, true> &p, const typename RealOf<T>::type (&cf)[9],
+                                             const typename Codec<T>::Raw (&x)[27], typename RealOf<T>::type (&v)[27])
 {
     using R = typename RealOf<T>::type;
     constexpr int d = NSLOT(-CX(I), -CY(I));
     if constexpr (d != 4 && CZ(I) == ZC) {
+        // the producer of the X value: this column (own mode) or x + c_I
+        const R add = cf[d] > R(0) ? p.template add_own<I>() : p.template add_pull<OPP(I)>();
+        const R xi = Codec<T>::template dec<I>(x[I], add);
         const R c = cf[d] > R(0) ? cf[d] : -cf[d];
-        v[I] = c * v[I] + (R(1) - c) * x[I];
+        v[I] = c * v[I] + (R(1) - c) * xi;
     }
-    if constexpr (I + 1 < 27) wall_combine<T, ZC, I + 1>(cf, x, v);
+    if constexpr (I + 1 < 27) wall_combine<T, ZC, I + 1>(p, cf, x, v);
 }
 
 // WALL: interpolated wall (coefficients at p.bc); else halfway bounce-back
@@ -368,13 +415,13 @@ __device__ __forceinline__ void gather(const Pull<T, WALL> &p, unsigned zo, unsi
                 const double c = p.bc[d * p.P];
                 cf[d] = (p.wall & (1u << d)) ? R(c) : R(1);
             }
-            R x[27];
+            typename Codec<T>::Raw x[27];
             wall_loads<T, FORM, -1>(p, cf, zo, zmo, zpo, x);
-            wall_combine<T, -1>(cf, x, g);
+            wall_combine<T, -1>(p, cf, x, g);
             wall_loads<T, FORM, 0>(p, cf, zo, zmo, zpo, x);
-            wall_combine<T, 0>(cf, x, g);
+            wall_combine<T, 0>(p, cf, x, g);
             wall_loads<T, FORM, 1>(p, cf, zo, zmo, zpo, x);
-            wall_combine<T, 1>(cf, x, g);
+            wall_combine<T, 1>(p, cf, x, g);
         }
     }
 }

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
     const bool owned = valid && (code & FUSED_OWNED);
     const int k = valid ? (code & ~FUSED_OWNED) : 0;
     __shared__ float lref[href_lds_floats<T, FUSED_BOX>()];
-    const Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, nullptr, g.href,
+    Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, nullptr, g.href,
                                    lref + 27 * threadIdx.x);
     const Shape<float> sh = shape_of<float>(g, b, k);
     const long long n = *g.step_dev + step_off;
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
         if (valid) {
             const unsigned zo = (unsigned)zs * rowb;
             const unsigned zmo = (unsigned)wrap_m(zs, g.nz) * rowb, zpo = (unsigned)wrap_p(zs, g.nz) * rowb;
+            pull_opaque<true>(p);
             gather<T, FORM_S, false>(p, zo, zmo, zpo, v);
             collide<T>(g, v, sig1, sh, zs);
             storage_round<T>(p, v);

@@ -20,7 +20,7 @@ namespace lbm {
 
 // (the FP32 interpolated-wall variant asks for the bounce-back variant's 4
 // waves per SIMD: without the hint it lands one register above that budget;
-// the FP16 one, with its 30 reference registers, would spill under it)
+// the FP16 one would spill under it, or under a budget of 3 waves)
 template <typename T, int BLOCK, bool WALL>
 __global__ __launch_bounds__(BLOCK) LBM_OCCUPANCY __attribute__((amdgpu_waves_per_eu(WALL && sizeof(T) == 4 ? 4 : 1)))
 void k_step(const Geom g, const Tiles t, const T *__restrict__ src, T *__restrict__ dst, int step_off)
@@ -210,8 +210,8 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     int cnt = 0;
     __shared__ float lref[href_lds_floats<T, BLOCK>()];
     if (active) {
-        const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k,
-                                                   g.bcoef, g.href, lref + 27 * threadIdx.x);
+        Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k,
+                                             g.bcoef, g.href, lref + 27 * threadIdx.x);
         const Shape<R> sh = shape_of<R>(g, tc.b, k);
         const unsigned xy = g.colxy[k];
         const int x = xy & 0xffff, y = xy >> 16;
@@ -221,6 +221,7 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
         const int z1 = min(z0 + t.zchunk, g.nz);
         for (int z = z0; z < z1; ++z) {
             R v[27];
+            pull_opaque<true>(p);
             gather<T, FORM, WALL>(p, (unsigned)z * rowb, (unsigned)wrap_m(z, g.nz) * rowb, (unsigned)wrap_p(z, g.nz) * rowb, v);
             R ax, ay, az;
             body_force<R>(g, z, sig, sh.px, sh.py, sh.pq, ax, ay, az);

@@ -75,7 +75,7 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
         const unsigned zo = (unsigned)z * rowb;
         const unsigned zmo = (unsigned)wrap_m(z, g.nz) * rowb, zpo = (unsigned)wrap_p(z, g.nz) * rowb;
         typename RealOf<T>::type v[27];
-        if constexpr (sizeof(T) == 2) lds_opaque(p.ref.pull);  // FP16 references stay in LDS
+        pull_opaque<WALL || MODE == STEP_AA_ODD>(p);  // FP16 (see there)
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         collide<T, KIND>(g, v, sig, sh, z);
         if constexpr (MODE == STEP_AB)
