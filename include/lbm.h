@@ -75,8 +75,9 @@ typedef struct {
     int64_t force_off_step; /* trigger force applied for steps n < force_off_step */
     int32_t storage;      /* 0: FP32 deviations, FP32 collision; 1: FP16 deviations, FP32
                              collision: a value g_i produced by the node of column y is
-                             stored as h = fp16_rne(fp32(2^k g_i - E_c(y))) and read as
-                             fp32(h / 2^k + E_c(y) / 2^k), with 2^k ~ 1/w_i (4, 16, 64, 256 for
+                             stored as h = fp16_rne(2^k g_i - E_c(y)) (one rounding of the
+                             exact difference) and read as fp32(h / 2^k + E_c(y) / 2^k)
+                             (one rounding), with 2^k ~ 1/w_i (4, 16, 64, 256 for
                              |c_i|^2 = 0, 1, 2, 3) and the column's reference E_c(y) =
                              fp32(32/27 d_c(u0(y))), c = c_z of population i, d_c the
                              per-axis factor of the equilibrium (d_0 = -3u^2/2, d_+-1 = +-3u

@@ -145,23 +145,25 @@ template <> struct Codec<double> {
         __builtin_nontemporal_store(v, reinterpret_cast<double *>(base + off));
     }
 };
-// FP16 encode and decode, each conversion an instruction of its own: an FP32
-// FMA, then the round-to-nearest-even conversion (folded into one mixed-
-// precision FMA the rounding would differ between kernels compiled apart),
-// and the conversion back before its FMA (folded into a mixed-precision FMA
-// that reads the loaded half directly, the compiler waits for each load
-// before issuing the next)
+// FP16 encode and decode, written out so that every kernel rounds alike.
+// The encode is one mixed-precision FMA that rounds s v - E once, to the
+// nearest half (v_fma_mixlo_f16; left to itself the compiler forms it in
+// some kernels and an FP32 FMA plus a conversion, two roundings, in others).
+// The decode converts the loaded half exactly, then one FP32 FMA (folded
+// into a mixed-precision FMA that reads the loaded half, the scheduler
+// interleaves the loads with their uses and the two-buffer step runs 25%
+// slower, measured).  The scale is a uniform operand; the stored half sits
+// zero-extended in a register of its own (see Raw).
 __device__ __forceinline__ unsigned short h_encode(float v, float scale, float ref)
 {
-    const float r = fmaf(v, scale, -ref);
     unsigned h;
-    asm("v_cvt_f16_f32 %0, %1" : "=v"(h) : "v"(r));
+    asm("v_fma_mixlo_f16 %0, %1, %2, -%3" : "=v"(h) : "v"(v), "s"(scale), "v"(ref));
     return (unsigned short)(h & 0xffffu);
 }
-__device__ __forceinline__ float h_decode(unsigned short raw, float inv_scale, float addend)
+__device__ __forceinline__ float h_decode(unsigned raw, float inv_scale, float addend)
 {
     float f;
-    asm("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"((unsigned)raw));
+    asm("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"(raw));
     return fmaf(f, inv_scale, addend);
 }
 template <> struct Codec<__half> {
@@ -178,7 +180,7 @@ template <> struct Codec<__half> {
     }
     template <int I> __device__ static __forceinline__ float dec(Raw r, float addend = 0.f)
     {
-        return h_decode((unsigned short)r, H_INV_SCALE(I), addend);
+        return h_decode(r, H_INV_SCALE(I), addend);
     }
     template <int I> __device__ static __forceinline__ void st(char *base, unsigned off, float v, float ref = 0.f)
     {

@@ -32,10 +32,13 @@ constexpr int kAdjZChunk = LBM_ADJ_ZCHUNK;   // z planes per thread for the adjo
 constexpr int kMaxRing = 4096;               // ring points of the coherent-structure sampling
 constexpr int kDefaultZChunk2 = 32;          // output planes per workgroup of the two-step kernel
 // default threads per block by storage (turbulent pipe, graph replays: FP32
-// 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256); the interpolated
-// wall is best at 256 threads and 2 planes (1.244 ms vs 1.281 at 512)
+// 1.146 ms at 512 vs 1.164 ms at 256; FP16 best at 256); with the
+// interpolated wall FP32 is best at 256 threads and 2 planes (1.244 ms vs
+// 1.281 at 512), FP16 at 64 threads and 16 planes (paper pipe: 1.222 ms vs
+// 1.422 at 256 threads: the waves with wall columns take longer, and a
+// workgroup holds its slot until its slowest wave ends)
 constexpr int kDefaultBlock[3] = {512, 256, 256};
-constexpr int kDefaultBlockWall = 256, kDefaultZChunkWall = 2;
+constexpr int kDefaultBlockWall[3] = {256, 64, 256}, kDefaultZChunkWall[3] = {2, 16, 2};
 // default z planes per thread by storage (measured on the 192^2 x 1152 pipe:
 // FP32 1.173 ms at 1 plane vs 1.209 ms at 4; FP16 best at 8)
 constexpr int kDefaultZChunk[3] = {1, 8, 2};
@@ -114,10 +117,10 @@ int build_layout(const lbm_config *cfg, Layout &L)
     if (c.radius > 0.0 && c.radius > 0.5 * (std::min(c.nx, c.ny) - 1))
         return bad("radius must be <= (min(nx, ny) - 1) / 2 so that the outer ring of the box is solid");
     const int sidx = (c.storage >= 0 && c.storage <= 2) ? c.storage : 0;
-    const bool wall_fp32 = c.wall == 1 && c.storage == 0;
-    const int block = c.block ? c.block : (wall_fp32 ? kDefaultBlockWall : kDefaultBlock[sidx]);
+    const bool iwall = c.wall == 1;
+    const int block = c.block ? c.block : (iwall ? kDefaultBlockWall[sidx] : kDefaultBlock[sidx]);
     if (block != 64 && block != 128 && block != 256 && block != 512) return bad("block must be 64, 128, 256 or 512");
-    const int zchunk = c.zchunk ? c.zchunk : (wall_fp32 ? kDefaultZChunkWall : kDefaultZChunk[sidx]);
+    const int zchunk = c.zchunk ? c.zchunk : (iwall ? kDefaultZChunkWall[sidx] : kDefaultZChunk[sidx]);
     if (zchunk < 1 || zchunk > 64) return bad("zchunk must be in 1..64");
 
     L.colmap.assign((size_t)c.nx * c.ny, -1);

@@ -41,8 +41,9 @@ SEED, AMP = 2024, 0.02
 
 
 # FP16 storage codec (include/lbm.h): a value g of population i produced by
-# column y is held as h = fp16_rne(fp32(2^k g - E_c(y))) and read as
-# fp32(h / 2^k + E_c(y) / 2^k), 2^k by shell, c = c_z of i
+# column y is held as h = fp16_rne(2^k g - E_c(y)) (one rounding of the exact
+# difference) and read as fp32(h / 2^k + E_c(y) / 2^k), 2^k by shell, c = c_z
+# of i
 FP16_SCALE = np.array([4.0 if s == 0 else 16.0 if s == 1 else 64.0 if s == 2 else 256.0
                        for s in (0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3, 3)])
 
@@ -63,8 +64,9 @@ def _czi(c):
 
 def _fp16_round(g, s, E):
     """What FP16 storage returns for the FP32 value g of scale s and reference E."""
-    r = np.float32(np.float64(np.float32(g)) * s - np.float64(E))
-    h = np.float64(np.float16(r))
+    # 2^k g - E is exact in FP64 (FP32 operands, power-of-two scale); numpy
+    # rounds FP64 to FP16 directly, once
+    h = np.float64(np.float16(np.float64(np.float32(g)) * s - np.float64(E)))
     return np.float64(np.float32(h / s + np.float64(E) / s))
 
 
