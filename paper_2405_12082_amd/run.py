@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -39,6 +40,15 @@ import numpy as np
 def _series(dominant) -> np.ndarray:
     """The first pipe's dominant modes: ints (resumed) and device tensors [batch]."""
     return np.array([d if isinstance(d, int) else int(d[0].item()) for d in dominant], dtype=np.int64)
+
+
+def _write(path, result):
+    """Write a result JSON atomically (a partial one stays readable if the run
+    is stopped while writing the next)."""
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        f.write(json.dumps(result))
+    os.replace(tmp, path)
 
 
 def _save(path, p, samples, profile, dominant, spec_sum, spec_n):
@@ -52,7 +62,8 @@ def _save(path, p, samples, profile, dominant, spec_sum, spec_n):
 def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: int = 10000,
         storage: int = 0, wall: int | None = None, log=print, modes_every: int = 0, modes_from: int = 0,
         r0_frac: float = 0.78, ntheta: int = 1024, mmax: int = 10, spinup_steps: int = 0,
-        spinup_storage: int | None = None, save: str | None = None, resume: str | None = None) -> dict:
+        spinup_storage: int | None = None, save: str | None = None, resume: str | None = None,
+        out_path: str | None = None, partial_every: int = 0) -> dict:
     import math
 
     import torch
@@ -117,6 +128,44 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
         p.set_populations(g, n)
         del g
         torch.cuda.empty_cache()
+
+    def summary(n_done):
+        """The result so far (also written every partial_every steps)."""
+        acc = p.profile_read()
+        if prof_host is not None:
+            acc = acc + prof_host
+        prof = radial_profiles(acc[0], cfg) if samples else None
+        out = {"preset": preset, "steps": steps, "steps_done": n_done, "stats_from": stats_from, "every": every,
+               "samples": samples, "storage": storage, "spinup_steps": spinup_steps, "spinup_storage": spinup_storage,
+               "wall": cfg["wall"], "fluid_nodes": nf,
+               "params": {k: cfg[k] for k in ("nx", "ny", "nz", "radius", "tau", "accel_z", "u_tau", "period",
+                                              "force_off_step", "n_modes")},
+               "amplitudes": np.asarray(amps).tolist(), "wall_time_s": round(time.perf_counter() - t0, 1)}
+        series = _series(dominant) if dominant else None
+        if dominant:
+            out["modes"] = {
+                "every": modes_every, "from": modes_from, "r0": r0, "ntheta": ntheta, "mmax": mmax,
+                "series": series.tolist(), "mean_spectrum": (spec_sum.cpu().numpy() / spec_n).tolist()}
+        if dominant and series.min() >= 1:  # 0: a ring without fluctuations
+            u_conv = float(np.interp(r0, prof["r"], prof["mean"])) if prof is not None else float("nan")
+            out["modes"].update({
+                "occupation": np.bincount(series, minlength=mmax + 1)[1:].tolist(),
+                "transition_matrix": H.transition_matrix(series, mmax).tolist(),
+                "ck": [{"order": d, "eigenvalues": lam.tolist(), "markov_prediction": pred.tolist()}
+                       for d, lam, pred in H.ck_test(series, mmax)],
+                "self_correlation_mean": H.self_correlation(series, mmax, min(200, len(series) // 4))[1].tolist(),
+                "streamwise_lengths": {str(k): v for k, v in
+                                       H.streamwise_lengths(series, mmax, modes_every, u_conv).items()},
+            })
+        if prof is not None:
+            ut = cfg["u_tau"]
+            prof = {k: np.asarray(v).tolist() for k, v in prof.items()}
+            prof["y_plus"] = ((cfg["radius"] - np.asarray(prof["r"])) * ut / nu).tolist()
+            prof["U_plus"] = (np.asarray(prof["mean"]) / ut).tolist()
+            prof["rms_plus"] = (np.asarray(prof["rms"]) / ut).tolist()
+            out["profiles"] = prof
+        return out
+
     last_t, last_n = time.perf_counter(), n
     while n < steps:
         k = min(chunk, steps - n)
@@ -146,41 +195,13 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
             last_t, last_n = now, n
             if d[4] != 0 or not np.isfinite(d[0]):
                 raise FloatingPointError(f"non-finite populations at step {n}")
-    acc = p.profile_read()
-    if prof_host is not None:
-        acc = acc + prof_host
+            if out_path and partial_every and n % partial_every == 0 and n < steps:
+                _write(out_path, summary(n))
+            last_t = time.perf_counter()
     if save:
-        _save(save, p, samples, acc, dominant, spec_sum, spec_n)
-    prof = radial_profiles(acc[0], cfg) if samples else None
-    out = {"preset": preset, "steps": steps, "stats_from": stats_from, "every": every, "samples": samples,
-           "storage": storage, "wall": cfg["wall"], "fluid_nodes": nf,
-           "params": {k: cfg[k] for k in ("nx", "ny", "nz", "radius", "tau", "accel_z", "u_tau", "period",
-                                          "force_off_step", "n_modes")},
-           "amplitudes": np.asarray(amps).tolist(), "wall_time_s": round(time.perf_counter() - t0, 1)}
-    if dominant:
-        series = _series(dominant)
-        out["modes"] = {
-            "every": modes_every, "from": modes_from, "r0": r0, "ntheta": ntheta, "mmax": mmax,
-            "series": series.tolist(), "mean_spectrum": (spec_sum.cpu().numpy() / spec_n).tolist()}
-    if dominant and series.min() >= 1:  # 0: a ring without fluctuations
-        u_conv = float(np.interp(r0, prof["r"], prof["mean"])) if prof is not None else float("nan")
-        out["modes"].update({
-            "occupation": np.bincount(series, minlength=mmax + 1)[1:].tolist(),
-            "transition_matrix": H.transition_matrix(series, mmax).tolist(),
-            "ck": [{"order": d, "eigenvalues": lam.tolist(), "markov_prediction": pred.tolist()}
-                   for d, lam, pred in H.ck_test(series, mmax)],
-            "self_correlation_mean": H.self_correlation(series, mmax, min(200, len(series) // 4))[1].tolist(),
-            "streamwise_lengths": {str(k): v for k, v in
-                                   H.streamwise_lengths(series, mmax, modes_every, u_conv).items()},
-        })
-    if prof is not None:
-        ut = cfg["u_tau"]
-        prof = {k: np.asarray(v).tolist() for k, v in prof.items()}
-        prof["y_plus"] = ((cfg["radius"] - np.asarray(prof["r"])) * ut / nu).tolist()
-        prof["U_plus"] = (np.asarray(prof["mean"]) / ut).tolist()
-        prof["rms_plus"] = (np.asarray(prof["rms"]) / ut).tolist()
-        out["profiles"] = prof
-    return out
+        acc = p.profile_read()
+        _save(save, p, samples, acc if prof_host is None else acc + prof_host, dominant, spec_sum, spec_n)
+    return summary(n)
 
 
 def main(argv=None) -> int:
@@ -202,19 +223,19 @@ def main(argv=None) -> int:
     ap.add_argument("--save", default=None, help="archive the run's state and statistics at its end (.npz)")
     ap.add_argument("--resume", default=None, help="continue from an archive written by --save")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--partial-every", type=int, default=0,
+                    help="also write the result so far to --out every this many steps")
     a = ap.parse_args(argv)
     stats_from = a.stats_from if a.stats_from is not None else a.steps // 2
     res = run(a.preset, a.steps, stats_from, a.every, a.progress, a.storage, a.wall,
               log=lambda s: print(s, flush=True), modes_every=a.modes_every,
               modes_from=a.modes_from if a.modes_from is not None else stats_from, r0_frac=a.r0_frac,
               ntheta=a.ntheta, mmax=a.mmax, spinup_steps=a.spinup_steps, spinup_storage=a.spinup_storage,
-              save=a.save, resume=a.resume)
-    text = json.dumps(res)
+              save=a.save, resume=a.resume, out_path=a.out, partial_every=a.partial_every)
     if a.out:
-        with open(a.out, "w") as f:
-            f.write(text)
+        _write(a.out, res)
     else:
-        print(text, flush=True)
+        print(json.dumps(res), flush=True)
     return 0
 
 

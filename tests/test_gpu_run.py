@@ -78,7 +78,11 @@ def test_run_save_resume_continues_bitwise(P, tmp_path):
     from paper_2405_12082_amd import run
     kw = dict(every=100, progress=200, log=lambda s: None, modes_every=20, modes_from=200, ntheta=256, mmax=10)
     whole = run.run("precision_ref", 400, 100, save=str(tmp_path / "whole.npz"), **kw)
-    run.run("precision_ref", 200, 100, save=str(tmp_path / "half.npz"), **kw)
+    run.run("precision_ref", 200, 100, save=str(tmp_path / "half.npz"), out_path=str(tmp_path / "part.json"),
+            partial_every=100, **dict(kw, progress=100))
+    import json
+    part = json.load(open(tmp_path / "part.json"))  # written at step 100 (the last one is the caller's)
+    assert part["steps_done"] == 100 and part["samples"] == 1 and len(part["profiles"]["mean"]) > 0
     resumed = run.run("precision_ref", 400, 100, resume=str(tmp_path / "half.npz"),
                       save=str(tmp_path / "resumed.npz"), **kw)
     a, b = np.load(tmp_path / "whole.npz"), np.load(tmp_path / "resumed.npz")
