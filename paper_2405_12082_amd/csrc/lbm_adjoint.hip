@@ -78,7 +78,8 @@ template <typename R> struct PopAdj {
 };
 
 // population part: sum_i mu_i d/d(rho, u, a) [ (f^eq_i - w_i) + F_i/2 ]
-template <typename R, int I = 0>
+// (SPLIT: the forward's weights, see weigh)
+template <typename R, bool SPLIT, int I = 0>
 __device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y, const AxisR<R> &Z, R ax, R ay, R az,
                                             const R (&mu)[27], PopAdj<R> &s)
 {
@@ -94,7 +95,7 @@ __device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y
     const R dax = ax * hx * eyz + ay * pxy + az * pxz;         // d api / d u_x
     const R day = ax * pxy + ay * hy * exz + az * pyz;
     const R daz = ax * pxz + ay * pyz + az * hz * exy;
-    const R wm = weigh<R>(I, mu[I], R(0));  // the forward's weights (split in FP32, as there)
+    const R wm = weigh<R, SPLIT>(I, mu[I], R(0));  // the forward's weights
     s.Sr += wm * (pi + R(0.5) * api);
     s.Sux += wm * (px + R(0.5) * dax);
     s.Suy += wm * (py + R(0.5) * day);
@@ -102,7 +103,7 @@ __device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y
     s.Sax += wm * px;
     s.Say += wm * py;
     s.Saz += wm * pz;
-    if constexpr (I + 1 < 27) pop_adjoint<R, I + 1>(X, Y, Z, ax, ay, az, mu, s);
+    if constexpr (I + 1 < 27) pop_adjoint<R, SPLIT, I + 1>(X, Y, Z, ax, ay, az, mu, s);
 }
 
 // D_k = <mu, d_k>, the columns 4..8 of the inverse moment matrix
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
             for (int i = 0; i < 27; ++i) mu[i] = R(0);
         }
         PopAdj<R> s = {0, 0, 0, 0, 0, 0, 0};
-        pop_adjoint<R>(X, Y, Z, ax, ay, az, mu, s);
+        pop_adjoint<R, sizeof(T) != 2>(X, Y, Z, ax, ay, az, mu, s);
         R D[5] = {0, 0, 0, 0, 0};
         dual_dots<R>(mu, D);
         R Dp[5];
