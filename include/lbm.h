@@ -253,6 +253,18 @@ int lbm_diagnostics(lbm_ctx *ctx, double *host_out);
  * Errors: LBM_EINVAL for a negative or non-finite limit. */
 int lbm_set_watchdog(lbm_ctx *ctx, double mass_rel_tol);
 
+/* Bounds checks of a checked build (liblbm_checked.so, built from the same
+ * sources with LBM_CHECKED=1): the step, observer, ring and adjoint kernels
+ * test every population load and store of their gather and store paths
+ * against the extent of its population, and every neighbour-table entry and
+ * column index against the table; a violation sets a bit and skips the
+ * access.  *flags receives the bits recorded since lbm_init (1: neighbour
+ * entry out of range, 2: load, 4: store, 8: column or node index); *checked
+ * (may be NULL) 1 for a checked build, 0 for the release build, whose flags
+ * are always 0.  Synchronises the stream.
+ * Errors: LBM_EINVAL for a NULL flags pointer; LBM_EHIP. */
+int lbm_check_flags(lbm_ctx *ctx, uint32_t *flags, int32_t *checked);
+
 /* Add the current state's streamwise-velocity power sums to the per-column
  * FP64 accumulators: sum over z of u_z, u_z^2, u_z^3, u_z^4 and the count
  * (statistics of Eq. (urmsformula), pooled over z).  Async. */

@@ -59,17 +59,30 @@ class LbmError(RuntimeError):
         self.code = code
 
 
-_lib = None
+CHECKED_LIB_PATH = os.path.join(HERE, "liblbm_checked.so")
+_libs = {}
 
 
 def lib():
     """The loaded library (raises if ``liblbm.so`` has not been built)."""
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_2405_12082_amd/build.py)")
-    L = C.CDLL(LIB_PATH)
+    return load(LIB_PATH)
+
+
+def checked_lib():
+    """The checked build (device-side bounds tests, ``lbm_check_flags``),
+    loaded beside the release library in its own namespace."""
+    return load(CHECKED_LIB_PATH)
+
+
+def load(path):
+    """A library built from these sources at ``path``, with the signatures
+    set (each path loaded once; ctypes loads it with local symbols, so two
+    builds coexist in one process)."""
+    if path in _libs:
+        return _libs[path]
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run paper_2405_12082_amd/build.py)")
+    L = C.CDLL(path)
     vp, i32, i64, dp, fp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double), C.c_void_p
     cfgp = C.POINTER(LbmConfig)
     sig = {
@@ -103,6 +116,7 @@ def lib():
         "lbm_ring_sample": ([vp, C.c_double, i32, vp], C.c_int),
         "lbm_ring_spectrum": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
         "lbm_ring_spectrum_static": ([vp, i32, i32, i32, i32, vp, vp, vp, vp], C.c_int),
+        "lbm_check_flags": ([vp, C.POINTER(C.c_uint32), C.POINTER(i32)], C.c_int),
         "lbm_last_error": ([vp], C.c_char_p),
         "lbm_destroy": ([vp], None),
     }
@@ -110,7 +124,7 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
-    _lib = L
+    _libs[path] = L
     return L
 
 

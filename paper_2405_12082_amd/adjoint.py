@@ -28,10 +28,11 @@ class EnergyAdjoint:
     precision: "fp32" (default: adjoint state and vector-Jacobian arithmetic
     in FP32, gradient accumulation in FP64) or "fp64"; the forward model is
     the configured stepper (FP64 forward storage requires "fp64").
+    library: the loaded library to run (default: the release build).
     """
 
     def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
-                 device="cuda", stream=None, precision: str = "fp32"):
+                 device="cuda", stream=None, precision: str = "fp32", library=None):
         if not (0 <= obs_begin < obs_end):
             raise ValueError("need 0 <= obs_begin < obs_end")
         if precision not in ("fp32", "fp64"):
@@ -46,6 +47,7 @@ class EnergyAdjoint:
         self.ring = None
         self.timing = {}
         self.runs = 0  # forward runs so far: the checkpoints belong to the last one
+        self.library = library
 
     @property
     def last_step(self) -> int:
@@ -54,7 +56,7 @@ class EnergyAdjoint:
     def _new_pipe(self, amps):
         if self.pipe is not None:
             self.pipe.close()
-        self.pipe = Pipe(self.cfg, amps, device=self.device, stream=self.stream)
+        self.pipe = Pipe(self.cfg, amps, device=self.device, stream=self.stream, library=self.library)
         return self.pipe
 
     def objective(self, amps, keep_checkpoints: bool = False) -> np.ndarray:

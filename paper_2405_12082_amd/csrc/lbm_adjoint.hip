@@ -156,10 +156,13 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     if (k >= g.ncol) return;
     int col[9];
 #pragma unroll
-    for (int d = 0; d < 9; ++d) col[d] = g.nbr[d * g.P + k];
+    for (int d = 0; d < 9; ++d) {
+        col[d] = g.nbr[d * g.P + k];
+        if (!check_ok(g.check, col[d] >= -1 && col[d] < g.P, CHK_NBR)) col[d] = k;
+    }
     __shared__ float lref[href_lds_floats<T, BLOCK>()];
     Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
-                                               k, g.bcoef, g.href, lref + 27 * threadIdx.x);
+                                               k, g.bcoef, g.href, lref + 27 * threadIdx.x, g.check);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
     using W = typename RealOf<T>::type;  // the forward step's arithmetic type
     const Shape<W> sh = shape_of<W>(g, b, k);

@@ -16,7 +16,24 @@
 
 #include "lbm_internal.h"
 
+// Checked builds (LBM_CHECKED, see lbm_internal.h): every population load
+// and store of the gather and store helpers below and every neighbour-table
+// entry they use is tested against its extent; a violation sets a bit of
+// the device word Geom::check and the access is skipped (a load returns 0).
+// Release builds compile the tests away.
 namespace lbm {
+
+enum CheckBit : unsigned { CHK_NBR = 1u, CHK_LOAD = 2u, CHK_STORE = 4u, CHK_INDEX = 8u };
+// true when ok; otherwise (checked builds) records bit in *flags
+__device__ __forceinline__ bool check_ok(unsigned *flags, bool ok, unsigned bit)
+{
+    if constexpr (LBM_CHECKED) {
+        if (!ok && flags) atomicOr(flags, bit);
+        return ok;
+    } else {
+        return true;
+    }
+}
 
 // D3Q27 velocities in the appendix order (rest, faces, xy/xz/yz edges, corners).
 __host__ __device__ constexpr int CX(int i)
@@ -241,7 +258,11 @@ template <typename T, bool WALL = false> struct Pull {
     const double *bc;   // interpolated wall: coefficient of slot d at bc[d * P] (0 for fluid slots)
     int P;
     HRef<T> ref;
+    unsigned *chk;      // checked builds: the violation flags
     using R = typename RealOf<T>::type;
+    // checked builds: a byte offset within one population's region
+    __device__ __forceinline__ bool ok_load(unsigned off) const { return check_ok(chk, off < pbytes, CHK_LOAD); }
+    __device__ __forceinline__ bool ok_store(unsigned off) const { return check_ok(chk, off < pbytes, CHK_STORE); }
     // decode addend of the value population I receives (pull or bounce-back)
     template <int I> __device__ __forceinline__ R add_pull() const
     {
@@ -268,17 +289,20 @@ template <typename T, bool WALL = false> struct Pull {
 template <typename T, bool WALL = false>
 __device__ __forceinline__ Pull<T, WALL> make_pull(const T *pipe, size_t pstride, const int *nbr, int P, int k,
                                                    const double *bcoef = nullptr, const float *href = nullptr,
-                                                   float *lds = nullptr)
+                                                   float *lds = nullptr, unsigned *chk = nullptr)
 {
     Pull<T, WALL> p;
     p.base = reinterpret_cast<const char *>(pipe);
     p.pbytes = pstride * sizeof(T);
     p.own = (unsigned)k * sizeof(T);
     p.wall = 0;
+    p.chk = chk;
+    check_ok(chk, k >= 0 && k < P, CHK_INDEX);
     int src[9];
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
-        const int c = nbr[d * P + k];
+        int c = nbr[d * P + k];
+        if (!check_ok(chk, c >= -1 && c < P, CHK_NBR)) c = k;
         src[d] = c >= 0 ? c : k;
         p.colo[d] = (unsigned)src[d] * sizeof(T);
         if (c < 0) p.wall |= 1u << d;
@@ -327,6 +351,7 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T, WALL>
 {
     if constexpr (FORM == FORM_N) {
         // g_I(x) itself, produced by x - c_I (or by x, as g*_opp(I), where x - c_I is solid)
+        if (!p.ok_load(zo + p.own)) return 0;
         return Codec<T>::template ld<I>(p.base + I * p.pbytes, zo + p.own, p.template add_pull<I>());
     } else {
         constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
@@ -338,8 +363,11 @@ __device__ __forceinline__ typename RealOf<T>::type pull_one(const Pull<T, WALL>
             // population I is fixed per column, bounce-back or not)
             const bool bb = p.wall & (1u << d);
             const char *b = p.base + (size_t)(bb ? OPP(here) : here) * p.pbytes;
-            return Codec<T>::template ld<I>(b, bb ? zo + p.own : zs + p.colo[d], p.template add_pull<I>());
+            const unsigned off = bb ? zo + p.own : zs + p.colo[d];
+            if (!p.ok_load(off)) return 0;
+            return Codec<T>::template ld<I>(b, off, p.template add_pull<I>());
         }
+        if (!p.ok_load(zs + p.colo[d]) || !p.ok_load(zo + p.own)) return 0;
         typename RealOf<T>::type v =
             Codec<T>::template ld<I>(p.base + here * p.pbytes, zs + p.colo[d], p.template add_pull<I>());
         if constexpr (d != 4) {
@@ -378,7 +406,7 @@ __device__ __forceinline__ void wall_loads(const Pull<T, true> &p, const typenam
             const unsigned off = own_mode ? zo + p.own : zf + p.colo[8 - d];
             // own mode: population I at this column; far mode: population
             // opp(I) at the neighbour x + c_I, the column opp(I) pulls from
-            x[I] = Codec<T>::raw(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off);
+            if (p.ok_load(off)) x[I] = Codec<T>::raw(p.base + (own_mode ? here : OPP(here)) * p.pbytes, off);
         }
     }
     if constexpr (I + 1 < 27) wall_loads<T, FORM, ZC, I + 1>(p, cf, zo, zmo, zpo, x);
@@ -436,7 +464,7 @@ template <typename T, bool WALL, int I = 0>
 __device__ __forceinline__ void store_all(char *pipe, const Pull<T, WALL> &p, unsigned off,
                                           const typename RealOf<T>::type (&g)[27])
 {
-    Codec<T>::template st<I>(pipe + I * p.pbytes, off, g[I], p.template ref_own<I>());
+    if (p.ok_store(off)) Codec<T>::template st<I>(pipe + I * p.pbytes, off, g[I], p.template ref_own<I>());
     if constexpr (I + 1 < 27) store_all<T, WALL, I + 1>(pipe, p, off, g);
 }
 
@@ -446,7 +474,7 @@ template <typename T, int I = 0>
 __device__ __forceinline__ void store_swapped(char *pipe, const Pull<T> &p, unsigned off,
                                               const typename RealOf<T>::type (&g)[27])
 {
-    Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, off, g[I], p.template ref_own<I>());
+    if (p.ok_store(off)) Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, off, g[I], p.template ref_own<I>());
     if constexpr (I + 1 < 27) store_swapped<T, I + 1>(pipe, p, off, g);
 }
 
@@ -461,10 +489,12 @@ __device__ __forceinline__ void store_push(char *pipe, const Pull<T> &p, unsigne
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
     constexpr int d = NSLOT(cx, cy);
     const unsigned zt = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
-    if (d != 4 && (p.wall & (1u << d)))
-        Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, zo + p.own, g[I], p.template ref_own<I>());
-    else
+    if (d != 4 && (p.wall & (1u << d))) {
+        if (p.ok_store(zo + p.own))
+            Codec<T>::template st<I>(pipe + OPP(I) * p.pbytes, zo + p.own, g[I], p.template ref_own<I>());
+    } else if (p.ok_store(zt + p.colo[d])) {
         Codec<T>::template st<I>(pipe + I * p.pbytes, zt + p.colo[d], g[I], p.template ref_own<I>());
+    }
     if constexpr (I + 1 < 27) store_push<T, I + 1>(pipe, p, zo, zmo, zpo, g);
 }
 

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(FUSED_BOX) void k_step2(const Geom g, const Tiles2 
     const int k = valid ? (code & ~FUSED_OWNED) : 0;
     __shared__ float lref[href_lds_floats<T, FUSED_BOX>()];
     Pull<T> p = make_pull<T>(src + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, nullptr, g.href,
-                                   lref + 27 * threadIdx.x);
+                                   lref + 27 * threadIdx.x, g.check);
     const Shape<float> sh = shape_of<float>(g, b, k);
     const long long n = *g.step_dev + step_off;
     const float sig1 = sigma_of<float>(g, n), sig2 = sigma_of<float>(g, n + 1);

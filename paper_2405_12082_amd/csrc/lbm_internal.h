@@ -5,6 +5,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Checked builds (-DLBM_CHECKED=1, liblbm_checked.so): device-side bounds
+// tests on the gather, store and table accesses (lbm_device.h), their
+// violations reported by lbm_check_flags.  0: the release build.
+#ifndef LBM_CHECKED
+#define LBM_CHECKED 0
+#endif
+
 namespace lbm {
 
 // z-invariant geometry and forcing tables, all in the caller's workspace
@@ -34,6 +41,7 @@ struct Geom {
     // c_z = 0, +1, -1 (d_c the per-axis equilibrium factor at the column's
     // initial velocity u0); null for FP32 / FP64 storage
     const float *href;
+    unsigned *check;  // checked builds: bounds-violation flags (CheckBit), one word
 };
 
 // tile decomposition of a launch: BLOCK consecutive columns x zchunk planes x pipe

@@ -211,10 +211,11 @@ __global__ __launch_bounds__(BLOCK) void k_observe(const Geom g, const Tiles t, 
     __shared__ float lref[href_lds_floats<T, BLOCK>()];
     if (active) {
         Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k,
-                                             g.bcoef, g.href, lref + 27 * threadIdx.x);
+                                             g.bcoef, g.href, lref + 27 * threadIdx.x, g.check);
         const Shape<R> sh = shape_of<R>(g, tc.b, k);
         const unsigned xy = g.colxy[k];
-        const int x = xy & 0xffff, y = xy >> 16;
+        int x = xy & 0xffff, y = xy >> 16;
+        if (!check_ok(g.check, x < g.nx && y < g.ny, CHK_INDEX)) x = y = 0;
         const size_t plane = (size_t)g.nx * g.ny;
         const unsigned rowb = (unsigned)g.P * sizeof(T);
         const int z0 = tc.zc * t.zchunk;

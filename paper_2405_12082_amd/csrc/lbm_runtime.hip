@@ -57,6 +57,7 @@ struct Layout {
     size_t state_bytes = 0;
     // workspace offsets
     size_t off_state[2], off_box, off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
+    size_t off_check = 0;  // bounds-violation flags of a checked build (one word)
     size_t off_fshape64, off_ztab64, off_sigma64;  // FP64 storage only
     size_t off_href;                               // FP16 storage only
     size_t off_diag_part, off_diag_out, off_prof_part, off_prof_acc, off_energy_part, off_energy_out;
@@ -201,6 +202,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     L.off_href = c.storage == 1 ? take(3 * P * sizeof(float)) : 0;
     L.off_step = take(sizeof(long long));
     L.off_step2 = take(sizeof(long long));
+    L.off_check = take(sizeof(unsigned));
     L.off_bar = take(32 * sizeof(unsigned) * ((size_t)cfg->batch + 1));
     L.off_ring_nodes = take((size_t)kMaxRing * 4 * sizeof(int));
     L.off_ring_idx = take((size_t)kMaxRing * 4 * sizeof(int));
@@ -658,9 +660,11 @@ int lbm_init(const lbm_config *cfg, const double *amps, void *workspace, size_t 
     G.sigma64 = g.storage == 2 ? (const double *)(ws + L.off_sigma64) : nullptr;
     G.kind = 2 * g.collision + g.equilibrium;
     G.href = g.storage == 1 ? (const float *)(ws + L.off_href) : nullptr;
+    G.check = (unsigned *)(ws + L.off_check);
 
     c->step = 0;
     e = launch_set_step((long long *)(ws + L.off_step), 0, 0, c->stream);
+    if (e == hipSuccess) e = launch_fill(ws + L.off_check, sizeof(unsigned), c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_state[0], L.state_bytes, c->stream);  // padding reads as 0
     if (e == hipSuccess && L.off_state[1] != L.off_state[0]) e = launch_fill(ws + L.off_state[1], L.state_bytes, c->stream);
     if (e == hipSuccess) e = launch_fill(ws + L.off_prof_acc, B * P * 5 * sizeof(double), c->stream);
@@ -885,6 +889,18 @@ int lbm_set_populations(lbm_ctx *c, const float *g, int64_t step)
     c->mass_ref.clear();
     HIPCHK(c, launch_set_pops(c->cfg.storage, c->form(step), c->geom, g, c->state(step), c->stream));
     HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), step, 0, c->stream));
+    return LBM_OK;
+}
+
+int lbm_check_flags(lbm_ctx *c, uint32_t *flags, int32_t *checked)
+{
+    CHECK_CTX(c);
+    if (!flags) return fail(c, LBM_EINVAL, "lbm_check_flags: NULL output");
+    unsigned v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->ws + c->L.off_check, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *flags = v;
+    if (checked) *checked = LBM_CHECKED;
     return LBM_OK;
 }
 

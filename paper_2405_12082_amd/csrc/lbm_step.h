@@ -62,7 +62,8 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
 {
     const int k = tc.k;
     Pull<T, WALL> p =
-        make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef, g.href, lref);
+        make_pull<T, WALL>(src + (size_t)tc.b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef, g.href, lref,
+                           g.check);
     using R = typename RealOf<T>::type;
     const Shape<R> sh = shape_of<R>(g, tc.b, k);
     const R sig = sigma_of<R>(g, n);

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_ring(const Geom g, const RingArgs r, co
     for (int u = threadIdx.x; u < r.n_nodes; u += 256) {
         const int col = r.nodes[u];
         const Pull<T, WALL> p = make_pull<T, WALL>(state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, col,
-                                                   g.bcoef, g.href, lref + 27 * threadIdx.x);
+                                                   g.bcoef, g.href, lref + 27 * threadIdx.x, g.check);
         R v[27];
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
         R ax, ay, az;

@@ -23,14 +23,16 @@ class Pipe:
 
     cfg:  dict (or keywords) with the ``lbm_config`` fields.
     amps: [batch][2*n_modes] trigger-force amplitudes (acceleration units).
+    library: the loaded library to run (``_lib.lib()``, the default, or
+    ``_lib.checked_lib()``).
     """
 
-    def __init__(self, cfg: dict | None = None, amps=None, device="cuda", stream=None, **kw):
+    def __init__(self, cfg: dict | None = None, amps=None, device="cuda", stream=None, library=None, **kw):
         d = dict(cfg or {})
         d.update(kw)
         self.cfg_dict = d
         self.cfg = make_config(**d)
-        self.lib = _lib.lib()
+        self.lib = library if library is not None else _lib.lib()
         self.layout = _lib.describe(self.cfg)
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -149,6 +151,13 @@ class Pipe:
         """Make diagnostics() fail (LBM_ENAN) when a pipe's mass drifts from its
         reference (the next diagnostics call) by more than mass_rel_tol; 0: off."""
         self._check(self.lib.lbm_set_watchdog(self._ctx, float(mass_rel_tol)), "lbm_set_watchdog")
+
+    def check_flags(self) -> tuple[int, bool]:
+        """Bounds-check violations recorded by a checked build since init
+        (see ``lbm_check_flags``), and whether this library is one."""
+        flags, checked = C.c_uint32(), C.c_int32()
+        self._check(self.lib.lbm_check_flags(self._ctx, C.byref(flags), C.byref(checked)), "lbm_check_flags")
+        return int(flags.value), bool(checked.value)
 
     def energy(self) -> np.ndarray:
         out = np.zeros(self.cfg.batch)
