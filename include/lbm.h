@@ -330,8 +330,10 @@ int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *
 
 /* Measurement aid: enqueue n copies of the current state buffer into the
  * other buffer with the launch geometry of lbm_step (27 aligned loads and 27
- * non-temporal stores per fluid node, no arithmetic): the practical HBM
- * bandwidth ceiling of the step's access pattern.  Leaves the state
+ * non-temporal stores per fluid node, no arithmetic): the HBM rate of the
+ * step's access pattern alone, a reference point for the step (which can
+ * run faster: the step kernel's loads and arithmetic overlap differently).
+ * Leaves the state
  * unchanged (the copy goes to the spare buffer; with the AA pattern the
  * buffer is copied onto itself).  Async. */
 int lbm_stream_copy(lbm_ctx *ctx, int32_t n);

@@ -109,7 +109,7 @@ class Pipe:
         self._check(self.lib.lbm_step_persistent_graph(self._ctx, int(n), int(k)), "lbm_step_persistent_graph")
 
     def stream_copy(self, n: int = 1):
-        """n copies of the state with the step's launch geometry (bandwidth ceiling)."""
+        """n copies of the state with the step's launch geometry (the access pattern without arithmetic)."""
         self._check(self.lib.lbm_stream_copy(self._ctx, int(n)), "lbm_stream_copy")
 
     @property
