@@ -51,12 +51,19 @@ def _write(path, result):
     os.replace(tmp, path)
 
 
-def _save(path, p, samples, profile, dominant, spec_sum, spec_n):
+def _fingerprint(cfg, every, modes_every, r0_frac, ntheta, mmax) -> str:
+    """What a resumed run must share with the archived one: the
+    configuration and the sampling."""
+    return json.dumps({"cfg": {k: cfg[k] for k in sorted(cfg)}, "every": every, "modes_every": modes_every,
+                       "r0_frac": r0_frac, "ntheta": ntheta, "mmax": mmax}, sort_keys=True, default=str)
+
+
+def _save(path, p, samples, profile, dominant, spec_sum, spec_n, fingerprint):
     """Archive of a run in progress (see the module notes)."""
     blob, step = p.save()
     np.savez(path, state=blob.cpu().numpy(), step=step, samples=samples, profile=profile,
              dominant=_series(dominant), spec_sum=np.zeros(0) if spec_sum is None else spec_sum.cpu().numpy(),
-             spec_n=spec_n)
+             spec_n=spec_n, fingerprint=np.array(fingerprint))
 
 
 def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: int = 10000,
@@ -94,8 +101,11 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
     dominant, spec_sum, spec_n = [], None, 0
     prof_host = None  # statistics of earlier processes (resume)
     n = 0
+    fingerprint = _fingerprint(cfg, every, modes_every, r0_frac, ntheta, mmax)
     if resume:
         arc = np.load(resume)
+        if str(arc["fingerprint"]) != fingerprint:
+            raise ValueError(f"{resume}: archived with another configuration or sampling")
         blob = torch.from_numpy(arc["state"]).to(p.device)
         if blob.numel() != p.state_bytes:
             raise ValueError(f"{resume}: the state does not match this configuration")
@@ -200,7 +210,8 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
             last_t = time.perf_counter()
     if save:
         acc = p.profile_read()
-        _save(save, p, samples, acc if prof_host is None else acc + prof_host, dominant, spec_sum, spec_n)
+        _save(save, p, samples, acc if prof_host is None else acc + prof_host, dominant, spec_sum, spec_n,
+              fingerprint)
     return summary(n)
 
 

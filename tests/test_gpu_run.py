@@ -85,6 +85,8 @@ def test_run_save_resume_continues_bitwise(P, tmp_path):
     assert part["steps_done"] == 100 and part["samples"] == 1 and len(part["profiles"]["mean"]) > 0
     resumed = run.run("precision_ref", 400, 100, resume=str(tmp_path / "half.npz"),
                       save=str(tmp_path / "resumed.npz"), **kw)
+    with pytest.raises(ValueError, match="another configuration"):
+        run.run("precision_ref", 400, 100, resume=str(tmp_path / "half.npz"), **dict(kw, every=50))
     a, b = np.load(tmp_path / "whole.npz"), np.load(tmp_path / "resumed.npz")
     assert int(a["step"]) == int(b["step"]) == 400
     assert np.array_equal(a["state"], b["state"])
