@@ -56,6 +56,8 @@ def self_correlation(modes, n_modes: int, max_lag: int):
     occ = f[:, 0] > 0
     fn = np.zeros_like(f)
     fn[occ] = f[occ] / f[occ, :1]
+    if not occ.any():  # no mode comes and goes (a constant series): undefined
+        return fn, np.full(max_lag + 1, np.nan)
     return fn, fn[occ].mean(axis=0)
 
 
