@@ -122,7 +122,7 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
         # the first steps in another storage, then the state through the dense populations
         q = Pipe(dict(cfg, storage=spinup_storage), amps)
         while n < spinup_steps:
-            k = min(chunk, spinup_steps - n)
+            k = min(chunk - n % chunk, spinup_steps - n)  # whole chunks from chunk multiples on
             q.step_graph(k, chunk) if k == chunk else q.step(k)
             n += k
             if n % progress == 0 or n == spinup_steps:
@@ -178,7 +178,9 @@ def run(preset: str, steps: int, stats_from: int, every: int = 100, progress: in
 
     last_t, last_n = time.perf_counter(), n
     while n < steps:
-        k = min(chunk, steps - n)
+        # steps up to the next multiple of chunk (a spin-up or an archive may
+        # end between two), so that every sampling step is reached
+        k = min(chunk - n % chunk, steps - n)
         if k == chunk:
             p.step_graph(k, chunk)
         else:

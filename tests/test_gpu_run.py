@@ -99,18 +99,20 @@ def test_run_save_resume_continues_bitwise(P, tmp_path):
 
 
 def test_run_fp16_spinup_hands_over_the_state(P):
-    """An FP16 spin-up of 200 steps, then FP32: the handed-over state is the
-    FP16 run's (the first FP32 diagnostics equal the FP16 run's mass to FP32
-    rounding of the export) and the run stays finite with its mass kept."""
+    """An FP16 spin-up of 210 steps (not a multiple of the sampling
+    interval), then FP32: the handed-over state is the FP16 run's (the first
+    FP32 diagnostics equal the FP16 run's mass to FP32 rounding of the
+    export), the sampling steps are still reached, and the run stays finite
+    with its mass kept."""
     from paper_2405_12082_amd import run
     lines = []
     res = run.run("precision_ref", 400, 300, every=100, progress=100, log=lines.append,
-                  spinup_steps=200, spinup_storage=1)
+                  spinup_steps=210, spinup_storage=1)
     import json
     recs = [json.loads(s) for s in lines]
     spin = [r for r in recs if "spinup_step" in r]
     main = [r for r in recs if "step" in r]
-    assert [r["spinup_step"] for r in spin] == [100, 200]
+    assert [r["spinup_step"] for r in spin] == [100, 200, 210]
     assert [r["step"] for r in main] == [300, 400]
     assert all(r["non_finite"] == 0 for r in recs)
     assert abs(main[0]["mass"] - spin[-1]["mass"]) < 1e-6
