@@ -165,7 +165,8 @@ def _events(stream):
 
 
 def leg_fp16(steps=500, storage=1, pattern=0, wall=0, preset="turbulent", fused=None):
-    """The turbulent pipe with FP16 scaled-deviation storage (108 B per update)."""
+    """Step rate of a preset in a storage form, buffer pattern and wall (the
+    fp16 leg: the turbulent pipe in FP16 storage, 108 B per update)."""
     import torch
     import lbm_inputs as LI
     import paper_2405_12082_amd as P
@@ -229,15 +230,18 @@ def leg_bouzidi(steps=500):
 
 def leg_paper(steps=300, ntheta=1024, mmax=10, reps=50):
     """The paper's own pipe, 300x300x600 (R = 149.5), FP32, with its wall
-    (the interpolation of Eqs. (fbc1)/(fbc2)) and its k_theta = 2 trigger;
-    plus the cost of one coherent-structure sample (Section II.C: u_z on
-    r = 0.78 R at every plane, transform of the azimuthal correlation,
-    dominant mode)."""
+    (the interpolation of Eqs. (fbc1)/(fbc2)) and its k_theta = 2 trigger,
+    and the same in FP16 storage (the form of the long runs); plus the cost
+    of one coherent-structure sample (Section II.C: u_z on r = 0.78 R at
+    every plane, transform of the azimuthal correlation, dominant mode)."""
     import torch
     import lbm_inputs as LI
     import paper_2405_12082_amd as P
     r = leg_fp16(steps, storage=0, pattern=0, wall=1, preset="paper")
     r["workload"] = "paper pipe 300x300x600 R=149.5, interpolated wall"
+    torch.cuda.empty_cache()
+    r["fp16"] = leg_fp16(steps, storage=1, pattern=0, wall=1, preset="paper")
+    torch.cuda.empty_cache()
     cfg = LI.preset("paper")
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
