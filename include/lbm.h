@@ -99,8 +99,11 @@ typedef struct {
     double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
     int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state and
                              arithmetic, 2 FP64 adjoint state and arithmetic */
-    int32_t block;        /* threads per block: 64, 128, 256, 512 (0 = default) */
-    int32_t zchunk;       /* z planes per thread: 1..64 (0 = default) */
+    int32_t block;        /* threads per block: 64, 128, 256, 512 (0 = default: 512 for FP32,
+                             256 for FP16 and FP64; with wall = 1, 256 for FP32 and FP64, 64
+                             for FP16) */
+    int32_t zchunk;       /* z planes per thread: 1..64 (0 = default: 1 for FP32, 8 for FP16,
+                             2 for FP64; with wall = 1, 2 for FP32 and FP64, 16 for FP16) */
     int32_t xcd_remap;    /* workgroup -> tile order (workgroups go round-robin to the 8 XCDs):
                              0 dispatch order; 1 XCD x takes the x-th eighth of the tiles;
                              G in 2..4096: XCD x takes every eighth chunk of G consecutive
