@@ -142,7 +142,9 @@ typedef struct {
  * cross-section with no fluid column, radius > (min(nx,ny)-1)/2, unknown
  * storage/wall/pattern/init/collision/equilibrium values, block/zchunk out
  * of range, a comparison scheme with FP16 storage, the AA pattern or an
- * adjoint). */
+ * adjoint, a pipe whose state would hold 2^31 elements or more: 27 x the
+ * population stride, about 79 M fluid nodes; every element index of the
+ * kernels then fits 32 bits). */
 int lbm_describe(const lbm_config *cfg, lbm_layout *out);
 
 /* Device workspace size lbm_init needs for cfg.  Host only. */
