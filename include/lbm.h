@@ -142,9 +142,11 @@ typedef struct {
  * cross-section with no fluid column, radius > (min(nx,ny)-1)/2, unknown
  * storage/wall/pattern/init/collision/equilibrium values, block/zchunk out
  * of range, a comparison scheme with FP16 storage, the AA pattern or an
- * adjoint, a pipe whose state would hold 2^31 elements or more: 27 x the
- * population stride, about 79 M fluid nodes; every element index of the
- * kernels then fits 32 bits). */
+ * adjoint, a pipe one of whose populations would take 4 GiB or more: the
+ * population stride (about nz x the fluid columns) times 4 B (FP32), 2 B
+ * (FP16) or 8 B (FP64); in FP32 about 1.07 G fluid nodes, 116 GB per state
+ * buffer: the kernels use 64-bit pipe and population bases and 32-bit byte
+ * offsets within a population). */
 int lbm_describe(const lbm_config *cfg, lbm_layout *out);
 
 /* Device workspace size lbm_init needs for cfg.  Host only. */

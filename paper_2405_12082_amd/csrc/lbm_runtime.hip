@@ -165,11 +165,14 @@ int build_layout(const lbm_config *cfg, Layout &L)
     // of the turbulent pipe measured 1.4% slower so)
     L.pstride = (long long)c.nz * L.P;
     if (L.pstride % 4096 == 0) L.pstride += 37 * 64;
-    if (27 * L.pstride >= (1LL << 31)) {
-        std::snprintf(buf, sizeof buf, "pipe too large: 27 x population stride = %lld must be < 2^31", 27 * L.pstride);
+    L.elem = c.storage == 1 ? 2 : (c.storage == 2 ? 8 : 4);
+    // the kernels address the state with 64-bit pipe and population bases and
+    // 32-bit byte offsets within one population's region
+    if (L.pstride * L.elem >= (1LL << 32)) {
+        std::snprintf(buf, sizeof buf, "pipe too large: one population takes %lld bytes, must be < 4 GiB",
+                      L.pstride * L.elem);
         return bad(buf);
     }
-    L.elem = c.storage == 1 ? 2 : (c.storage == 2 ? 8 : 4);
     const long long pipe_elems = 27 * L.pstride;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
     if (c.xcd_remap < 0 || c.xcd_remap > 4096) return bad("xcd_remap must be in 0..4096");

@@ -165,3 +165,30 @@ def test_a_corrupt_neighbour_entry_is_caught(libs):
     flags, _ = p.check_flags()
     assert flags & 1 and not flags & ~1, f"{flags:#x}"
     p.close()
+
+
+def test_checked_build_on_a_pipe_beyond_2_31_elements(libs):
+    """The checked build on a pipe of more than 2^31 state elements (384^2 x
+    1024, R = 180, FP16 and FP32): no violation in 3 steps, and the state
+    equals the release build's bitwise (compared on the device)."""
+    import paper_2405_12082_amd as P
+    for storage in (1, 0):
+        cfg = dict(LI.preset("turbulent"), nx=384, ny=384, nz=1024, radius=180.0, storage=storage)
+        _log(f"checked build, 384^2 x 1024 pipe, storage {storage}")
+        ref = None
+        for k, lib in enumerate(libs):
+            p = P.Pipe(cfg, LI.preset_amplitudes(cfg), library=lib)
+            p.step(3)
+            flags, checked = p.check_flags()
+            assert flags == 0 and checked == (k == 1), (flags, checked)
+            g = p.populations()
+            p.close()
+            del p
+            if ref is None:
+                ref = g
+            else:
+                assert torch.equal(ref, g)
+            del g
+            torch.cuda.empty_cache()
+        del ref
+        torch.cuda.empty_cache()

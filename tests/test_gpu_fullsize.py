@@ -238,3 +238,14 @@ def test_adjoint_pipe_gradient_vs_central_differences(P):
     assert best["fwd32_adj64"] < 1e-4
     assert best["fwd64_adj64"] < 1e-6
     assert best["fwd32_adj32"] < 2e-4
+
+
+def test_pipe_beyond_2_31_state_elements_one_step_sampled_parity(P, oracle_mod):
+    """A pipe whose state holds more than 2^31 elements: 384^2 x 1024 with
+    R = 180, 104 M fluid nodes, 2.8 G elements per buffer (the kernels take
+    64-bit pipe and population bases and 32-bit byte offsets within one
+    population, 417 MB here); the one-step sampled parity above, FP32."""
+    cfg = dict(nx=384, ny=384, nz=1024, radius=180.0)
+    lay = P.describe(P.make_config(**dict(LI.preset("turbulent"), **cfg)))
+    assert 27 * lay.population_stride > 2 ** 31
+    _sampled_step_parity(P, oracle_mod, "turbulent", 301, **cfg)
