@@ -146,7 +146,8 @@ typedef struct {
  * population stride (about nz x the fluid columns) times 4 B (FP32), 2 B
  * (FP16) or 8 B (FP64); in FP32 about 1.07 G fluid nodes, 116 GB per state
  * buffer: the kernels use 64-bit pipe and population bases and 32-bit byte
- * offsets within a population). */
+ * offsets within a population), and with an adjoint the same limit on one
+ * population of the adjoint state (4 B for adjoint = 1, 8 B for 2). */
 int lbm_describe(const lbm_config *cfg, lbm_layout *out);
 
 /* Device workspace size lbm_init needs for cfg.  Host only. */

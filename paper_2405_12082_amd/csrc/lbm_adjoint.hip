@@ -31,31 +31,33 @@ namespace lbm {
 // Coefficient tables hold 0 for fluid slots, so the mode tests need no
 // neighbour masks.
 template <typename R, bool WALL, int J = 0>
-__device__ __forceinline__ void gather_transpose(const R *__restrict__ lam, int pstride, int P, const int (&col)[9],
-                                                 int k, int z, int zm, int zp, const double *bcoef, R (&mu)[27])
+__device__ __forceinline__ void gather_transpose(const Pull<R> &pl, unsigned zo, unsigned zmo, unsigned zpo,
+                                                 const double *bcoef, R (&mu)[27])
 {
-    constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
+    constexpr int cx = CX(J), cy = CY(J);
     constexpr int d = NSLOT(cx, cy);
-    const int zs = cz == 0 ? z : (cz > 0 ? zp : zm);
-    const int sc = col[d];
-    if (d == 4 || sc >= 0) {
-        mu[J] = lam[(size_t)J * pstride + (size_t)zs * P + sc];
-        if constexpr (WALL && d != 4) {
-            const double cf = bcoef[(size_t)d * P + sc];
-            if (cf < 0.0) mu[J] += R(1.0 + cf) * lam[(size_t)OPP(J) * pstride + (size_t)zs * P + sc];
-        }
-    } else {
-        mu[J] = lam[(size_t)OPP(J) * pstride + (size_t)z * P + k];
-        if constexpr (WALL) {
-            const double cf = bcoef[(size_t)d * P + k];
-            mu[J] *= R(cf > 0.0 ? cf : -cf);
-        }
-    }
+    // lambda_J(y + c_J), or lambda_opp(J)(y) where y + c_J is solid: the
+    // pull of population opp(J) with the slots swapped
+    mu[J] = pull_one<R, OPP(J), FORM_W, false>(pl, zo, zmo, zpo);
     if constexpr (WALL && d != 4) {
-        const double cf = bcoef[(size_t)(8 - d) * P + k];
-        if (cf > 0.0 && cf != 1.0) mu[J] += R(1.0 - cf) * lam[(size_t)J * pstride + (size_t)z * P + k];
+        constexpr int cz = CZ(J);
+        const unsigned zs = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
+        const bool solid = pl.wall & (1u << d);
+        const unsigned sc = pl.colo[d] / sizeof(R);  // the neighbour's column (this one where solid)
+        const double cf = bcoef[(size_t)d * pl.P + sc];
+        if (solid) {
+            mu[J] *= R(cf > 0.0 ? cf : -cf);
+        } else if (cf < 0.0) {
+            const unsigned off = zs + pl.colo[d];
+            if (pl.ok_load(off)) mu[J] += R(1.0 + cf) * Codec<R>::template ld<0>(pl.base + OPP(J) * pl.pbytes, off);
+        }
+        const double co = bcoef[(size_t)(8 - d) * pl.P + pl.own / sizeof(R)];
+        if (co > 0.0 && co != 1.0) {
+            const unsigned off = zo + pl.own;
+            if (pl.ok_load(off)) mu[J] += R(1.0 - co) * Codec<R>::template ld<0>(pl.base + J * pl.pbytes, off);
+        }
     }
-    if constexpr (J + 1 < 27) gather_transpose<R, WALL, J + 1>(lam, pstride, P, col, k, z, zm, zp, bcoef, mu);
+    if constexpr (J + 1 < 27) gather_transpose<R, WALL, J + 1>(pl, zo, zmo, zpo, bcoef, mu);
 }
 
 // per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
@@ -127,15 +129,15 @@ __device__ __forceinline__ void dual_dots(const R (&mu)[27], R (&D)[5])
 }
 
 template <typename R, int J = 0>
-__device__ __forceinline__ void write_lambda(R *__restrict__ lam, int pstride, size_t off, R Ldr, R Ljx, R Ljy, R Ljz,
+__device__ __forceinline__ void write_lambda(const Pull<R> &pl, char *lam, unsigned off, R Ldr, R Ljx, R Ljy, R Ljz,
                                              const R (&Dp)[5])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
     R v = Ldr + R(cx) * Ljx + R(cy) * Ljy + R(cz) * Ljz;
     v += R(cx * cy) * Dp[0] + R(cx * cz) * Dp[1] + R(cy * cz) * Dp[2];
     v += R(cx * cx - cy * cy) * Dp[3] + R(cx * cx - cz * cz) * Dp[4];
-    lam[(size_t)J * pstride + off] = v;
-    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(lam, pstride, off, Ldr, Ljx, Ljy, Ljz, Dp);
+    if (pl.ok_store(off)) Codec<R>::template st<J>(lam + J * pl.pbytes, off, v);
+    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(pl, lam, off, Ldr, Ljx, Ljy, Ljz, Dp);
 }
 
 #ifndef LBM_ADJ_WAVES_PER_EU
@@ -154,12 +156,6 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc + t.b0;
     const int k = kb * BLOCK + threadIdx.x;
     if (k >= g.ncol) return;
-    int col[9];
-#pragma unroll
-    for (int d = 0; d < 9; ++d) {
-        col[d] = g.nbr[d * g.P + k];
-        if (!check_ok(g.check, col[d] >= -1 && col[d] < g.P, CHK_NBR)) col[d] = k;
-    }
     __shared__ float lref[href_lds_floats<T, BLOCK>()];
     Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
                                                k, g.bcoef, g.href, lref + 27 * threadIdx.x, g.check);
@@ -167,8 +163,11 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     using W = typename RealOf<T>::type;  // the forward step's arithmetic type
     const Shape<W> sh = shape_of<W>(g, b, k);
     const W sig = sigma_of<W>(g, a.cursor);
-    const R *lin = (const R *)a.lam_in + (size_t)b * g.pipe;
-    R *lout = (R *)a.lam_out + (size_t)b * g.pipe;
+    // the adjoint state, addressed as the forward state (32-bit offsets within a population)
+    const Pull<R> pl = make_pull<R, false>((const R *)a.lam_in + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
+                                           k, nullptr, nullptr, nullptr, g.check);
+    char *lout = reinterpret_cast<char *>((R *)a.lam_out + (size_t)b * g.pipe);
+    const unsigned lrow = (unsigned)g.P * sizeof(R);
     const R om1 = R(1) - R(omega_of<W>(g));
     const R we = R(a.energy_weight);
     double G[3] = {0.0, 0.0, 0.0};
@@ -206,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
         R mu[27];
         if (a.has_next) {
-            gather_transpose<R, WALL>(lin, g.pstride, g.P, col, k, z, zm, zp, g.bcoef, mu);
+            gather_transpose<R, WALL>(pl, (unsigned)z * lrow, (unsigned)zm * lrow, (unsigned)zp * lrow, g.bcoef, mu);
         } else {
 #pragma unroll
             for (int i = 0; i < 27; ++i) mu[i] = R(0);
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const R sx = h * rho * s.Sax + Qax + h * Lux;
         const R sy = h * rho * s.Say + Qay + h * Luy;
         const R sz_ = h * rho * s.Saz + Qaz + h * Luz;
-        write_lambda<R>(lout, g.pstride, (size_t)z * g.P + k, Ldr, Ljx, Ljy, Ljz, Dp);
+        write_lambda<R>(pl, lout, (unsigned)z * lrow + pl.own, Ldr, Ljx, Ljy, Ljz, Dp);
         G[0] += cz * (double)sx;
         G[1] += cz * (double)sy;
         G[2] += sz * (double)sz_;

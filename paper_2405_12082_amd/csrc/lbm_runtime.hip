@@ -173,6 +173,13 @@ int build_layout(const lbm_config *cfg, Layout &L)
                       L.pstride * L.elem);
         return bad(buf);
     }
+    // the adjoint state (FP32 or FP64) is addressed the same way
+    const long long adj_elem = c.adjoint == 2 ? 8 : 4;
+    if (c.adjoint != 0 && L.pstride * adj_elem >= (1LL << 32)) {
+        std::snprintf(buf, sizeof buf, "pipe too large for the adjoint: one adjoint population takes %lld bytes, "
+                      "must be < 4 GiB", L.pstride * adj_elem);
+        return bad(buf);
+    }
     const long long pipe_elems = 27 * L.pstride;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
     if (c.xcd_remap < 0 || c.xcd_remap > 4096) return bad("xcd_remap must be in 0..4096");

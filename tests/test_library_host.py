@@ -119,3 +119,19 @@ def test_counter_based_generator_matches_sequential():
     a = LI.uniform01(11, 50)
     b = LI.hash_uniform(11, np.arange(50))
     assert np.array_equal(a, b)
+
+
+def test_population_size_limit():
+    """The kernels address one population's region with 32-bit byte offsets:
+    a population of the state (or of the adjoint state) must take < 4 GiB."""
+    def rc(**kw):
+        cfg = dict(LI.preset("turbulent"), nx=512, ny=512, radius=255.5, **kw)
+        return P.lib().lbm_describe(C.byref(P.make_config(**cfg)), C.byref(_lib.LbmLayout()))
+    # about 205,000 fluid columns: 4000 planes take 3.3 GB per FP32 population
+    assert rc(nz=4000) == _lib.LBM_OK
+    assert rc(nz=4000, adjoint=1) == _lib.LBM_OK
+    assert rc(nz=4000, adjoint=2) == _lib.LBM_EINVAL   # 6.6 GB per FP64 adjoint population
+    assert rc(nz=4000, storage=2) == _lib.LBM_EINVAL   # FP64 state
+    assert rc(nz=6000) == _lib.LBM_EINVAL
+    assert rc(nz=6000, storage=1) == _lib.LBM_OK       # FP16: 2.5 GB
+    assert rc(nz=6000, storage=1, adjoint=1) == _lib.LBM_EINVAL
