@@ -382,6 +382,28 @@ def leg_batched(steps=5000, graph_k=50, persistent_steps=1000):
             "state_finite": ok}
 
 
+def elementwise_add_rate(gib=4, reps=20):
+    """Read + write GB/s of torch.add(a, 1, out=b) over two FP32 tensors of
+    `gib` GiB each: the rate a plain streaming kernel reaches on this part
+    (one read and one write stream, no reuse)."""
+    import torch
+    n = gib << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.empty(n, device="cuda")
+    torch.add(a, 1.0, out=b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * 4 * n / (ms * 1e-3) / 1e9
+
+
 def leg_adjoint(fd_frac=1e-2):
     """Adjoint workload: 96x96x384 pipe (R = 45), 2000 steps, checkpoints
     every 100; gradient of the streamwise energy over steps 1501..2000 with
@@ -774,6 +796,12 @@ def main():
     }
     del pipe
     torch.cuda.empty_cache()
+    # second reference point: the streaming rate of a plain elementwise kernel
+    add_gbs = elementwise_add_rate()
+    out["roofline"]["elementwise_add_gbs"] = round(add_gbs, 1)
+    if traffic:
+        out["roofline"]["traffic_gbs"] = round(traffic / (kavg_ms * 1e-3) / 1e9, 1)
+        out["roofline"]["traffic_vs_add_rate"] = round(traffic / (kavg_ms * 1e-3) / 1e9 / add_gbs, 4)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     for leg in legs:
