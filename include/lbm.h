@@ -97,8 +97,8 @@ typedef struct {
                              adjoint (adjoint must be 0) */
     int32_t init;         /* 0: rest (g = 0); 1: log-law mean profile, f = f^eq(1, u_z(r)) */
     double u_tau;         /* friction velocity u* of the log-law profile (init = 1) */
-    int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state and
-                             arithmetic, 2 FP64 adjoint state and arithmetic */
+    int32_t adjoint;      /* adjoint buffers in the workspace: 0 none, 1 FP32 adjoint state,
+                             2 FP64 adjoint state (FP64 arithmetic in both) */
     int32_t block;        /* threads per block: 64, 128, 256, 512 (0 = default: 512 for FP32,
                              256 for FP16 and FP64; with wall = 1, 256 for FP32 and FP64, 64
                              for FP16) */
@@ -298,7 +298,8 @@ int lbm_load(lbm_ctx *ctx, const void *src, int64_t step);
  *     J = 1/W sum_{n in [obs_begin, obs_end)} E(f^n),
  *     E(f^n) = (1/N_f) sum_x 1/2 rho u_z^2 with u_z = j_z/rho + a_z(x, n)/2,
  * the time-averaged streamwise kinetic energy, W = obs_end - obs_begin.
- * The adjoint state lambda^n = dJ/df^n lives in the workspace (FP32 or FP64):
+ * The adjoint state lambda^n = dJ/df^n lives in the workspace (FP32 or FP64;
+ * the vector-Jacobian products are computed in FP64 in either case):
  *     lambda^c = (dC/df^c)^T S^T lambda^{c+1} + dE_c/df^c [c in window],
  * with lambda^{N+1} = 0 for the last state N = obs_end - 1.
  *

@@ -25,9 +25,10 @@ class EnergyAdjoint:
 
     cfg:   configuration dict (``lbm_config`` fields).
     obs_begin, obs_end: the window [obs_begin, obs_end) of J.
-    precision: "fp32" (default: adjoint state and vector-Jacobian arithmetic
-    in FP32, gradient accumulation in FP64) or "fp64"; the forward model is
-    the configured stepper (FP64 forward storage requires "fp64").
+    precision: the adjoint state's storage, "fp32" (default) or "fp64"; the
+    vector-Jacobian arithmetic and the gradient accumulation are FP64 in
+    both; the forward model is the configured stepper (FP64 forward storage
+    requires "fp64").
     library: the loaded library to run (default: the release build).
     """
 

@@ -15,9 +15,12 @@
 
 namespace lbm {
 
-// The adjoint is templated on R, the type of the adjoint state and of the
-// vector-Jacobian arithmetic (float or double); the forward state is decoded
-// to float as in the forward kernel, then promoted to R.
+// The adjoint state is stored as S (float or double); the vector-Jacobian
+// arithmetic is FP64 (R) for either: the forward state is decoded as in the
+// forward kernel and promoted, the adjoint state promoted on load and rounded
+// to S on store.  (With FP32 arithmetic the gradient of the 2000-step
+// adjoint workload is 1.4e-4 from central differences; with FP64 arithmetic
+// it is 3.6e-5 whether the state is stored in FP32 or FP64.)
 
 // mu = S^T lambda, the transpose of the pull.  Bounce-back wall: mu_j(y) =
 // lambda_j(y + c_j) if y + c_j is fluid, else lambda_opp(j)(y).  The
@@ -30,34 +33,34 @@ namespace lbm {
 //    (cf < 0): weight 1 + cf in that link (X = g*_j of the node behind it).
 // Coefficient tables hold 0 for fluid slots, so the mode tests need no
 // neighbour masks.
-template <typename R, bool WALL, int J = 0>
-__device__ __forceinline__ void gather_transpose(const Pull<R> &pl, unsigned zo, unsigned zmo, unsigned zpo,
+template <typename S, typename R, bool WALL, int J = 0>
+__device__ __forceinline__ void gather_transpose(const Pull<S> &pl, unsigned zo, unsigned zmo, unsigned zpo,
                                                  const double *bcoef, R (&mu)[27])
 {
     constexpr int cx = CX(J), cy = CY(J);
     constexpr int d = NSLOT(cx, cy);
     // lambda_J(y + c_J), or lambda_opp(J)(y) where y + c_J is solid: the
     // pull of population opp(J) with the slots swapped
-    mu[J] = pull_one<R, OPP(J), FORM_W, false>(pl, zo, zmo, zpo);
+    mu[J] = R(pull_one<S, OPP(J), FORM_W, false>(pl, zo, zmo, zpo));
     if constexpr (WALL && d != 4) {
         constexpr int cz = CZ(J);
         const unsigned zs = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
         const bool solid = pl.wall & (1u << d);
-        const unsigned sc = pl.colo[d] / sizeof(R);  // the neighbour's column (this one where solid)
+        const unsigned sc = pl.colo[d] / sizeof(S);  // the neighbour's column (this one where solid)
         const double cf = bcoef[(size_t)d * pl.P + sc];
         if (solid) {
             mu[J] *= R(cf > 0.0 ? cf : -cf);
         } else if (cf < 0.0) {
             const unsigned off = zs + pl.colo[d];
-            if (pl.ok_load(off)) mu[J] += R(1.0 + cf) * Codec<R>::template ld<0>(pl.base + OPP(J) * pl.pbytes, off);
+            if (pl.ok_load(off)) mu[J] += R(1.0 + cf) * R(Codec<S>::template ld<0>(pl.base + OPP(J) * pl.pbytes, off));
         }
-        const double co = bcoef[(size_t)(8 - d) * pl.P + pl.own / sizeof(R)];
+        const double co = bcoef[(size_t)(8 - d) * pl.P + pl.own / sizeof(S)];
         if (co > 0.0 && co != 1.0) {
             const unsigned off = zo + pl.own;
-            if (pl.ok_load(off)) mu[J] += R(1.0 - co) * Codec<R>::template ld<0>(pl.base + J * pl.pbytes, off);
+            if (pl.ok_load(off)) mu[J] += R(1.0 - co) * R(Codec<S>::template ld<0>(pl.base + J * pl.pbytes, off));
         }
     }
-    if constexpr (J + 1 < 27) gather_transpose<R, WALL, J + 1>(pl, zo, zmo, zpo, bcoef, mu);
+    if constexpr (J + 1 < 27) gather_transpose<S, R, WALL, J + 1>(pl, zo, zmo, zpo, bcoef, mu);
 }
 
 // per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
@@ -128,16 +131,16 @@ __device__ __forceinline__ void dual_dots(const R (&mu)[27], R (&D)[5])
     if constexpr (I + 1 < 27) dual_dots<R, I + 1>(mu, D);
 }
 
-template <typename R, int J = 0>
-__device__ __forceinline__ void write_lambda(const Pull<R> &pl, char *lam, unsigned off, R Ldr, R Ljx, R Ljy, R Ljz,
+template <typename S, typename R, int J = 0>
+__device__ __forceinline__ void write_lambda(const Pull<S> &pl, char *lam, unsigned off, R Ldr, R Ljx, R Ljy, R Ljz,
                                              const R (&Dp)[5])
 {
     constexpr int cx = CX(J), cy = CY(J), cz = CZ(J);
     R v = Ldr + R(cx) * Ljx + R(cy) * Ljy + R(cz) * Ljz;
     v += R(cx * cy) * Dp[0] + R(cx * cz) * Dp[1] + R(cy * cz) * Dp[2];
     v += R(cx * cx - cy * cy) * Dp[3] + R(cx * cx - cz * cz) * Dp[4];
-    if (pl.ok_store(off)) Codec<R>::template st<J>(lam + J * pl.pbytes, off, v);
-    if constexpr (J + 1 < 27) write_lambda<R, J + 1>(pl, lam, off, Ldr, Ljx, Ljy, Ljz, Dp);
+    if (pl.ok_store(off)) Codec<S>::template st<J>(lam + J * pl.pbytes, off, S(v));
+    if constexpr (J + 1 < 27) write_lambda<S, R, J + 1>(pl, lam, off, Ldr, Ljx, Ljy, Ljz, Dp);
 }
 
 #ifndef LBM_ADJ_WAVES_PER_EU
@@ -149,9 +152,10 @@ __device__ __forceinline__ void write_lambda(const Pull<R> &pl, char *lam, unsig
 #define LBM_ADJ_OCCUPANCY
 #endif
 
-template <typename T, typename R, int BLOCK, bool WALL>
+template <typename T, typename S, int BLOCK, bool WALL>
 __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
+    using R = double;
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc + t.b0;
     const int k = kb * BLOCK + threadIdx.x;
@@ -164,10 +168,10 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     const Shape<W> sh = shape_of<W>(g, b, k);
     const W sig = sigma_of<W>(g, a.cursor);
     // the adjoint state, addressed as the forward state (32-bit offsets within a population)
-    const Pull<R> pl = make_pull<R, false>((const R *)a.lam_in + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
+    const Pull<S> pl = make_pull<S, false>((const S *)a.lam_in + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
                                            k, nullptr, nullptr, nullptr, g.check);
-    char *lout = reinterpret_cast<char *>((R *)a.lam_out + (size_t)b * g.pipe);
-    const unsigned lrow = (unsigned)g.P * sizeof(R);
+    char *lout = reinterpret_cast<char *>((S *)a.lam_out + (size_t)b * g.pipe);
+    const unsigned lrow = (unsigned)g.P * sizeof(S);
     const R om1 = R(1) - R(omega_of<W>(g));
     const R we = R(a.energy_weight);
     double G[3] = {0.0, 0.0, 0.0};
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
         R mu[27];
         if (a.has_next) {
-            gather_transpose<R, WALL>(pl, (unsigned)z * lrow, (unsigned)zm * lrow, (unsigned)zp * lrow, g.bcoef, mu);
+            gather_transpose<S, R, WALL>(pl, (unsigned)z * lrow, (unsigned)zm * lrow, (unsigned)zp * lrow, g.bcoef, mu);
         } else {
 #pragma unroll
             for (int i = 0; i < 27; ++i) mu[i] = R(0);
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const R sx = h * rho * s.Sax + Qax + h * Lux;
         const R sy = h * rho * s.Say + Qay + h * Luy;
         const R sz_ = h * rho * s.Saz + Qaz + h * Luz;
-        write_lambda<R>(pl, lout, (unsigned)z * lrow + pl.own, Ldr, Ljx, Ljy, Ljz, Dp);
+        write_lambda<S, R>(pl, lout, (unsigned)z * lrow + pl.own, Ldr, Ljx, Ljy, Ljz, Dp);
         G[0] += cz * (double)sx;
         G[1] += cz * (double)sy;
         G[2] += sz * (double)sz_;

@@ -1,10 +1,13 @@
 """GPU discrete adjoint against the FP64 oracle adjoint and against central
 finite differences of the GPU forward model (needs an MI355X).
 
-Tolerances: the GPU gradient (FP32 forward and adjoint states, FP64
-gradient accumulation) agrees with the oracle's FP64 adjoint to 1e-4
-relative (max norm over the amplitudes) on a tiny pipe, and with central
-finite differences of its own forward model to 1e-4 relative (2-norm).
+Tolerances: the GPU gradient (FP32 forward states, FP32 or FP64 adjoint
+states, FP64 vector-Jacobian arithmetic and gradient accumulation) agrees
+with the oracle's FP64 adjoint to 1e-6 relative (max norm over the
+amplitudes) on a tiny pipe over 40 steps (the FP32 forward states' rounding,
+6e-8 relative per state), with the oracle's tangent over 2000 steps to 1e-5,
+and with central finite differences of its own forward model to 1e-4
+relative (2-norm).
 """
 import sys
 
@@ -38,7 +41,7 @@ TINY_AMPS = np.array([1e-4, 2e-4, 3e-4, 1.5e-4])
 
 
 @pytest.mark.parametrize("precision,wall,nz,storage,tol", [
-    ("fp32", 0, 8, 0, 1e-4), ("fp64", 0, 8, 0, 1e-4), ("fp32", 1, 8, 0, 1e-4), ("fp64", 1, 8, 0, 1e-4),
+    ("fp32", 0, 8, 0, 1e-6), ("fp64", 0, 8, 0, 1e-6), ("fp32", 1, 8, 0, 1e-6), ("fp64", 1, 8, 0, 1e-6),
     # FP64 storage: FP64 forward, adjoint and force tables, so the hand-derived
     # vector-Jacobian products meet the oracle's complex-step adjoint at
     # rounding level (measured 1e-12)
@@ -65,7 +68,7 @@ def test_adjoint_matches_oracle_adjoint(gpu, oracle_mod, precision, wall, nz, st
     assert err < tol
 
 
-@pytest.mark.parametrize("precision,tol,wall,storage", [("fp64", 1e-5, 0, 0), ("fp32", 1e-4, 0, 0), ("fp64", 1e-5, 1, 0),
+@pytest.mark.parametrize("precision,tol,wall,storage", [("fp64", 1e-5, 0, 0), ("fp32", 1e-5, 0, 0), ("fp64", 1e-5, 1, 0),
                                                       ("fp64", 1e-10, 0, 2), ("fp64", 1e-10, 1, 2)])
 def test_long_horizon_adjoint_matches_oracle_tangent(gpu, oracle_mod, precision, tol, wall, storage):
     """2000 steps of a 16x16x32 pipe (R = 7) with the adjoint workload's

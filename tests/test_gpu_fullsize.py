@@ -205,11 +205,10 @@ def test_adjoint_pipe_gradient_vs_central_differences(P):
     100), against central differences of the FP64-storage forward (a step of
     1% or 3% of the largest amplitude; differences of the FP32 forward move
     the state by only a few FP32 ulps and cannot resolve 1e-4).  Stated
-    accuracies: the FP32 forward with the FP64 adjoint state (the path the
-    benchmark times) within 1e-4 (measured 3.5e-5); the FP64 forward within
-    1e-6 (6.7e-8); the FP32 forward with the FP32 adjoint state within 2e-4
-    (measured 1.4e-4: it misses 1e-4, the FP32 adjoint state's own rounding
-    over 2000 reverse steps)."""
+    accuracies: the FP32 forward with the adjoint state stored in FP32 (the
+    path the benchmark times) or FP64, FP64 arithmetic in both, within 1e-4
+    (measured 3.6e-5 for both: what remains is the FP32 forward's own
+    trajectory); the FP64 forward within 1e-6 (6.7e-8)."""
     from paper_2405_12082_amd.adjoint import EnergyAdjoint
     cfg = LI.preset("adjoint")
     amps = LI.preset_amplitudes(cfg)
@@ -235,9 +234,9 @@ def test_adjoint_pipe_gradient_vs_central_differences(P):
             rel = np.linalg.norm(g - fd) / np.linalg.norm(fd)
             best[k] = min(best[k], rel)
             _log(f"eps = {frac:g} * max|amps|: {k} vs FD {rel:.3e}")
+    assert best["fwd32_adj32"] < 1e-4
     assert best["fwd32_adj64"] < 1e-4
     assert best["fwd64_adj64"] < 1e-6
-    assert best["fwd32_adj32"] < 2e-4
 
 
 def test_pipe_beyond_2_31_state_elements_one_step_sampled_parity(P, oracle_mod):
