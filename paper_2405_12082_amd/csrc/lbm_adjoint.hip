@@ -33,15 +33,15 @@ namespace lbm {
 //    (cf < 0): weight 1 + cf in that link (X = g*_j of the node behind it).
 // Coefficient tables hold 0 for fluid slots, so the mode tests need no
 // neighbour masks.
-template <typename S, typename R, bool WALL, int J = 0>
+template <typename S, typename R, bool WALL, int J = 0, typename M>
 __device__ __forceinline__ void gather_transpose(const Pull<S> &pl, unsigned zo, unsigned zmo, unsigned zpo,
-                                                 const double *bcoef, R (&mu)[27])
+                                                 const double *bcoef, M (&mu)[27])
 {
     constexpr int cx = CX(J), cy = CY(J);
     constexpr int d = NSLOT(cx, cy);
     // lambda_J(y + c_J), or lambda_opp(J)(y) where y + c_J is solid: the
     // pull of population opp(J) with the slots swapped
-    mu[J] = R(pull_one<S, OPP(J), FORM_W, false>(pl, zo, zmo, zpo));
+    mu[J] = M(pull_one<S, OPP(J), FORM_W, false>(pl, zo, zmo, zpo));
     if constexpr (WALL && d != 4) {
         constexpr int cz = CZ(J);
         const unsigned zs = cz == 0 ? zo : (cz > 0 ? zpo : zmo);
@@ -64,7 +64,8 @@ __device__ __forceinline__ void gather_transpose(const Pull<S> &pl, unsigned zo,
 }
 
 // per-axis equilibrium factors 1 + d_c(u) and their u-derivatives (see the
-// forward collision): d_0 = -3u^2/2, d_+-1 = +-3u + 3u^2; d' and d'' below
+// forward collision): d_0 = -3u^2/2, d_+-1 = +-3u + 3u^2, their first
+// derivatives d'_0 = -3u, d'_+-1 = +-3 + 6u (the second, -3 and 6, are constants)
 template <typename R> struct AxisR {
     R e0, ep, em;   // 1 + d_c
     R q0, qp, qm;   // d'_c
@@ -75,48 +76,84 @@ template <typename R> __device__ __forceinline__ AxisR<R> axis_r(R u)
     return AxisR<R>{R(1) - R(1.5) * u2, R(1) + u3 + R(3) * u2, R(1) - u3 + R(3) * u2, -u3, R(3) + R(6) * u,
                     R(-3) + R(6) * u};
 }
-template <int C, typename R> __device__ __forceinline__ R esel(const AxisR<R> &a) { return C == 0 ? a.e0 : (C > 0 ? a.ep : a.em); }
-template <int C, typename R> __device__ __forceinline__ R qsel_r(const AxisR<R> &a) { return C == 0 ? a.q0 : (C > 0 ? a.qp : a.qm); }
 
 template <typename R> struct PopAdj {
     R Sr, Sux, Suy, Suz, Sax, Say, Saz;
 };
 
 // population part: sum_i mu_i d/d(rho, u, a) [ (f^eq_i - w_i) + F_i/2 ]
-// (SPLIT: the forward's weights, see weigh)
-template <typename R, bool SPLIT, int I = 0>
-__device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y, const AxisR<R> &Z, R ax, R ay, R az,
-                                            const R (&mu)[27], PopAdj<R> &s)
+// with f^eq_i - w_i = w_i (rho Pi_i - 1), Pi_i = e_x e_y e_z (one factor
+// 1 + d_c(u) per axis) and F_i = rho w_i a . grad_u Pi_i.  The weights
+// factor by axis too (w_i = w1(c_x) w1(c_y) w1(c_z), w1(0) = 2/3, w1(+-1) =
+// 1/6), so every term of the sum over the 27 populations is a product of one
+// factor per axis: w1 e, w1 q = w1 d'_c or w1 h = w1 d''_c of that axis.  The
+// sum is contracted one axis at a time (x, then y, then z): ten sums T_fgh =
+// sum_i mu_i (w1 f)(c_x) (w1 g)(c_y) (w1 h)(c_z) give every derivative.
+template <typename R> struct AxisW {
+    R e[3], q[3];  // w1(c) (1 + d_c(u)) and w1(c) d'_c(u) for c = 0, +1, -1
+};
+template <typename R> __device__ __forceinline__ AxisW<R> axis_w(const AxisR<R> &a)
 {
-    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    const R ex = esel<cx>(X), ey = esel<cy>(Y), ez = esel<cz>(Z);
-    const R qx = qsel_r<cx>(X), qy = qsel_r<cy>(Y), qz = qsel_r<cz>(Z);
-    const R hx = cx == 0 ? R(-3) : R(6), hy = cy == 0 ? R(-3) : R(6), hz = cz == 0 ? R(-3) : R(6);
-    const R eyz = ey * ez, exz = ex * ez, exy = ex * ey;
-    const R pi = ex * eyz;
-    const R px = qx * eyz, py = qy * exz, pz = qz * exy;      // d Pi / d u
-    const R api = ax * px + ay * py + az * pz;                // F_i / (rho w)
-    const R pxy = qx * qy * ez, pxz = qx * qz * ey, pyz = qy * qz * ex;
-    const R dax = ax * hx * eyz + ay * pxy + az * pxz;         // d api / d u_x
-    const R day = ax * pxy + ay * hy * exz + az * pyz;
-    const R daz = ax * pxz + ay * pyz + az * hz * exy;
-    const R wm = weigh<R, SPLIT>(I, mu[I], R(0));  // the forward's weights
-    s.Sr += wm * (pi + R(0.5) * api);
-    s.Sux += wm * (px + R(0.5) * dax);
-    s.Suy += wm * (py + R(0.5) * day);
-    s.Suz += wm * (pz + R(0.5) * daz);
-    s.Sax += wm * px;
-    s.Say += wm * py;
-    s.Saz += wm * pz;
-    if constexpr (I + 1 < 27) pop_adjoint<R, SPLIT, I + 1>(X, Y, Z, ax, ay, az, mu, s);
+    const R w0 = R(2) / R(3), w1 = R(1) / R(6);
+    return AxisW<R>{{w0 * a.e0, w1 * a.ep, w1 * a.em}, {w0 * a.q0, w1 * a.qp, w1 * a.qm}};
+}
+// w1(c) d''_c: d''_0 = -3, d''_+-1 = 6
+template <typename R> __device__ __forceinline__ constexpr R axis_h(int k) { return k == 0 ? R(-2) : R(1); }
+__host__ __device__ constexpr int cval(int k) { return k == 0 ? 0 : (k == 1 ? 1 : -1); }
+
+template <typename R, typename M>
+__device__ __forceinline__ void pop_adjoint(const AxisR<R> &X, const AxisR<R> &Y, const AxisR<R> &Z, R ax, R ay, R az,
+                                            const M (&mu)[27], PopAdj<R> &s)
+{
+    const AxisW<R> x = axis_w(X), y = axis_w(Y), z = axis_w(Z);
+    R eee = 0, qee = 0, eqe = 0, eeq = 0, hee = 0, ehe = 0, eeh = 0, qqe = 0, qeq = 0, eqq = 0;
+#pragma unroll
+    for (int kz = 0; kz < 3; ++kz) {
+        R Yee = 0, Yqe = 0, Yeq = 0, Yhe = 0, Yeh = 0, Yqq = 0;  // (x factor, y factor)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+            R Xe = 0, Xq = 0, Xh = 0;
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const R m = R(mu[IDX(cval(kx), cval(ky), cval(kz))]);
+                Xe += m * x.e[kx];
+                Xq += m * x.q[kx];
+                Xh += m * axis_h<R>(kx);
+            }
+            Yee += Xe * y.e[ky];
+            Yqe += Xq * y.e[ky];
+            Yeq += Xe * y.q[ky];
+            Yhe += Xh * y.e[ky];
+            Yeh += Xe * axis_h<R>(ky);
+            Yqq += Xq * y.q[ky];
+        }
+        eee += Yee * z.e[kz];
+        qee += Yqe * z.e[kz];
+        eqe += Yeq * z.e[kz];
+        eeq += Yee * z.q[kz];
+        hee += Yhe * z.e[kz];
+        ehe += Yeh * z.e[kz];
+        eeh += Yee * axis_h<R>(kz);
+        qqe += Yqq * z.e[kz];
+        qeq += Yqe * z.q[kz];
+        eqq += Yeq * z.q[kz];
+    }
+    const R h = R(0.5);
+    s.Sr = eee + h * (ax * qee + ay * eqe + az * eeq);            // d/d rho
+    s.Sux = qee + h * (ax * hee + ay * qqe + az * qeq);           // d/d u_x (then times rho)
+    s.Suy = eqe + h * (ax * qqe + ay * ehe + az * eqq);
+    s.Suz = eeq + h * (ax * qeq + ay * eqq + az * eeh);
+    s.Sax = qee;                                                  // d/d a (then times rho/2)
+    s.Say = eqe;
+    s.Saz = eeq;
 }
 
 // D_k = <mu, d_k>, the columns 4..8 of the inverse moment matrix
-template <typename R, int I = 0>
-__device__ __forceinline__ void dual_dots(const R (&mu)[27], R (&D)[5])
+template <typename R, int I = 0, typename M>
+__device__ __forceinline__ void dual_dots(const M (&mu)[27], R (&D)[5])
 {
     constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
-    const R m = mu[I];
+    const R m = R(mu[I]);
     if constexpr (SHELL(I) == 2) {
         if constexpr (cz == 0) D[0] += (cx * cy > 0 ? R(0.25) : R(-0.25)) * m;
         if constexpr (cy == 0) D[1] += (cx * cz > 0 ? R(0.25) : R(-0.25)) * m;
@@ -207,15 +244,18 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         const R inv = R(1) / rho;
         const R ux = jx * inv + R(0.5) * ax, uy = jy * inv + R(0.5) * ay, uz = jz * inv + R(0.5) * az;
         const AxisR<R> X = axis_r(ux), Y = axis_r(uy), Z = axis_r(uz);
-        R mu[27];
+        // the gathered adjoint values: without the interpolated wall they are
+        // the stored values themselves, kept in the storage type
+        using M = typename std::conditional<WALL, R, S>::type;
+        M mu[27];
         if (a.has_next) {
             gather_transpose<S, R, WALL>(pl, (unsigned)z * lrow, (unsigned)zm * lrow, (unsigned)zp * lrow, g.bcoef, mu);
         } else {
 #pragma unroll
-            for (int i = 0; i < 27; ++i) mu[i] = R(0);
+            for (int i = 0; i < 27; ++i) mu[i] = M(0);
         }
-        PopAdj<R> s = {0, 0, 0, 0, 0, 0, 0};
-        pop_adjoint<R, sizeof(T) != 2>(X, Y, Z, ax, ay, az, mu, s);
+        PopAdj<R> s;
+        pop_adjoint<R>(X, Y, Z, ax, ay, az, mu, s);
         R D[5] = {0, 0, 0, 0, 0};
         dual_dots<R>(mu, D);
         R Dp[5];
