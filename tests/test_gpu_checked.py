@@ -124,11 +124,12 @@ def test_comparison_schemes(libs, kind, wall):
     _both(libs, cfg, run)
 
 
+@pytest.mark.parametrize("storage", [0, 1])
 @pytest.mark.parametrize("wall", [0, 1])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_adjoint_with_recompute(libs, wall, precision):
+def test_adjoint_with_recompute(libs, wall, precision, storage):
     from paper_2405_12082_amd.adjoint import EnergyAdjoint
-    cfg = _cfg(wall=wall, nz=16)
+    cfg = _cfg(wall=wall, nz=16, storage=storage)
     grads = []
     for lib in libs:
         run = EnergyAdjoint(cfg, 20, 40, checkpoint_every=10, precision=precision, library=lib)
