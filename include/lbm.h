@@ -134,6 +134,9 @@ typedef struct {
     int64_t bytes_per_update;/* algorithmic HBM bytes per fluid-node update of lbm_step */
     int64_t population_stride; /* elements between the populations of one pipe: nz * plane_pitch,
                                   padded by 2368 when that is a multiple of 4096 */
+    int64_t record_bytes;    /* bytes of one moment record of lbm_recompute_moments (all pipes):
+                                [batch][4][population_stride] FP32 (FP64 for FP64 storage),
+                                rounded up to 256 */
 } lbm_layout;
 
 /* Check a configuration and report its layout.  Host only.
@@ -336,6 +339,33 @@ int lbm_energy_accumulate(lbm_ctx *ctx, double *acc);
  * The states are exactly those lbm_step would produce.  Two-buffer pattern
  * only (LBM_EINVAL otherwise).  Async. */
 int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *ring, size_t stride);
+
+/* Checkpoint-and-recompute with moment records: the collision depends on the
+ * state only through rho, j and the stress moments m_4..m_8 (appendix,
+ * Eqs. (m*)-(k*f*)), and its Jacobian only through rho and u, so the reverse
+ * step needs of each forward state f^c only rho - 1 and j = sum c_i f_i:
+ * 16 B per node (32 B in FP64) instead of the state's 108 B (216 B).
+ * lbm_recompute_moments: scratch[0] := start (a saved state of step s0; no
+ * copy when start == scratch), then n steps of the two-buffer pattern
+ * alternating between the two scratch states (device memory, stride bytes
+ * apart: stride >= lbm_state_bytes, multiple of 256), step j (state of step
+ * s0 + j) recording the moments of the state it consumes into records[j]
+ * (device memory, record_stride bytes apart: record_stride >=
+ * lbm_layout.record_bytes, multiple of 256; layout [batch][q][z P + k], q =
+ * rho - 1, j_x, j_y, j_z, each q a region of population_stride elements; in
+ * the collision's arithmetic type).  The states are exactly those lbm_step
+ * would produce; the context's own state is untouched.  start is scratch
+ * state 0 or outside both scratch states.  Two-buffer pattern and the
+ * paper's scheme only (LBM_EINVAL otherwise).  Async.
+ * lbm_adjoint_step_moments: lbm_adjoint_step with n records of
+ * lbm_recompute_moments (moments of f^{c-n+1} .. f^c in forward order,
+ * record_stride bytes apart) in place of the saved states; the same
+ * arithmetic from the recorded moments (the forward collision's own, in its
+ * arithmetic type) instead of FP64 sums of the gathered state.  Errors and
+ * cursor as lbm_adjoint_step.  Async. */
+int lbm_recompute_moments(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *scratch, size_t stride,
+                          void *records, size_t record_stride);
+int lbm_adjoint_step_moments(lbm_ctx *ctx, int32_t n, const void *records, size_t record_stride, double *grad);
 
 /* Measurement aid: enqueue n copies of the current state buffer into the
  * other buffer with the launch geometry of lbm_step (27 aligned loads and 27

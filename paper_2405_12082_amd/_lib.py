@@ -37,7 +37,7 @@ class LbmLayout(C.Structure):
     _fields_ = [
         ("n_fluid_columns", C.c_int64), ("plane_pitch", C.c_int64), ("n_fluid_nodes", C.c_int64),
         ("state_bytes", C.c_int64), ("workspace_bytes", C.c_int64), ("bytes_per_update", C.c_int64),
-        ("population_stride", C.c_int64),
+        ("population_stride", C.c_int64), ("record_bytes", C.c_int64),
     ]
 
 
@@ -113,6 +113,8 @@ def load(path):
         "lbm_energy": ([vp, dp], C.c_int),
         "lbm_energy_accumulate": ([vp, vp], C.c_int),
         "lbm_recompute": ([vp, vp, i64, i32, vp, C.c_size_t], C.c_int),
+        "lbm_recompute_moments": ([vp, vp, i64, i32, vp, C.c_size_t, vp, C.c_size_t], C.c_int),
+        "lbm_adjoint_step_moments": ([vp, i32, vp, C.c_size_t, vp], C.c_int),
         "lbm_ring_sample": ([vp, C.c_double, i32, vp], C.c_int),
         "lbm_ring_spectrum": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
         "lbm_ring_spectrum_static": ([vp, i32, i32, i32, i32, vp, vp, vp, vp], C.c_int),

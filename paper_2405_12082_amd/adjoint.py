@@ -30,14 +30,21 @@ class EnergyAdjoint:
     both; the forward model is the configured stepper (FP64 forward storage
     requires "fp64").
     library: the loaded library to run (default: the release build).
+    records: what the recompute keeps of each forward state for the reverse
+    steps: "moments" (default: rho - 1 and j, 16 B per node, the collision's
+    Jacobian needs no more) or "states" (the whole saved state, 108 B).
     """
 
     def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
-                 device="cuda", stream=None, precision: str = "fp32", library=None):
+                 device="cuda", stream=None, precision: str = "fp32", library=None, records: str = "moments"):
         if not (0 <= obs_begin < obs_end):
             raise ValueError("need 0 <= obs_begin < obs_end")
         if precision not in ("fp32", "fp64"):
             raise ValueError("precision must be 'fp32' or 'fp64'")
+        if records not in ("moments", "states"):
+            raise ValueError("records must be 'moments' or 'states'")
+        self.records = records
+        self.scratch = None
         self.cfg = dict(cfg, adjoint=2 if precision == "fp64" else 1)
         self.obs_begin, self.obs_end = int(obs_begin), int(obs_end)
         self.C = int(checkpoint_every)
@@ -99,16 +106,24 @@ class EnergyAdjoint:
         B, nq = p.cfg.batch, 2 * p.cfg.n_modes
         grad = torch.zeros((B, max(nq, 1)), dtype=torch.float64, device=self.device)
         N = self.last_step
-        if self.ring is None or self.ring.shape != (self.C, p.state_bytes):
-            self.ring = torch.empty((self.C, p.state_bytes), dtype=torch.uint8, device=self.device)
+        moments = self.records == "moments"
+        rec = p.record_bytes if moments else p.state_bytes
+        if self.ring is None or self.ring.shape != (self.C, rec):
+            self.ring = torch.empty((self.C, rec), dtype=torch.uint8, device=self.device)
+        if moments and (self.scratch is None or self.scratch.shape != (2, p.state_bytes)):
+            self.scratch = torch.empty((2, p.state_bytes), dtype=torch.uint8, device=self.device)
         p.adjoint_reset(self.obs_begin, self.obs_end)
         cursor = N
         while cursor >= 0:
             k = cursor // self.C
             start = k * self.C
             count = cursor - start + 1
-            p.recompute(self.ckpt[k], start, self.ring, count)   # the segment's states
-            p.adjoint_step(self.ring[:count], grad, count)
+            if moments:  # the segment's moment records
+                p.recompute_moments(self.ckpt[k], start, self.scratch, self.ring, count)
+                p.adjoint_step_moments(self.ring[:count], grad, count)
+            else:  # the segment's states
+                p.recompute(self.ckpt[k], start, self.ring, count)
+                p.adjoint_step(self.ring[:count], grad, count)
             cursor = start - 1
         e1.record()
         torch.cuda.synchronize()

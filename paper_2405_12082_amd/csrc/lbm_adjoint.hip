@@ -12,6 +12,7 @@
 // onto the trigger-force mode shapes of Eq. (TurbForce).
 #include "lbm_device.h"
 #include "lbm_internal.h"
+#include "lbm_step.h"
 
 namespace lbm {
 
@@ -189,19 +190,26 @@ __device__ __forceinline__ void write_lambda(const Pull<S> &pl, char *lam, unsig
 #define LBM_ADJ_OCCUPANCY
 #endif
 
-template <typename T, typename S, int BLOCK, bool WALL>
+// REC: the forward state's moments come from a record of the recording step
+// (a.rec, [b][4][population stride] of W) instead of a gather of the saved
+// state (a.state): 16 B (FP64 forward: 32 B) per node instead of 108 B, and
+// no forward-state gather in the kernel.
+template <typename T, typename S, int BLOCK, bool WALL, bool REC>
 __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom g, const Tiles t, const AdjointArgs a)
 {
     using R = double;
+    using W = typename RealOf<T>::type;  // the forward step's arithmetic type
     const int tile = xcd_tile(blockIdx.x, gridDim.x, t.xcd);
     const int kb = tile % t.nkb, rest = tile / t.nkb, zc = rest % t.nzc, b = rest / t.nzc + t.b0;
     const int k = kb * BLOCK + threadIdx.x;
     if (k >= g.ncol) return;
-    __shared__ float lref[href_lds_floats<T, BLOCK>()];
-    Pull<T, WALL> p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P,
-                                               k, g.bcoef, g.href, lref + 27 * threadIdx.x, g.check);
+    __shared__ float lref[REC ? 1 : href_lds_floats<T, BLOCK>()];
+    Pull<T, WALL> p{};
+    if constexpr (!REC)
+        p = make_pull<T, WALL>((const T *)a.state + (size_t)b * g.pipe, (size_t)g.pstride, g.nbr, g.P, k, g.bcoef,
+                               g.href, lref + 27 * threadIdx.x, g.check);
     const unsigned rowb = (unsigned)g.P * sizeof(T);
-    using W = typename RealOf<T>::type;  // the forward step's arithmetic type
+    const W *rec = REC ? (const W *)a.rec + (size_t)b * 4 * g.pstride + k : nullptr;
     const Shape<W> sh = shape_of<W>(g, b, k);
     const W sig = sigma_of<W>(g, a.cursor);
     // the adjoint state, addressed as the forward state (32-bit offsets within a population)
@@ -215,9 +223,6 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
     const int z0 = zc * t.zchunk, z1 = min(z0 + t.zchunk, g.nz);
     for (int z = z0; z < z1; ++z) {
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        W v[27];
-        pull_opaque<true>(p);
-        gather<T, FORM_S, WALL>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
         // the forward's z factors, for the projection of the sensitivities
         double cz, sz;
         if constexpr (sizeof(W) == 8) {
@@ -232,13 +237,27 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         body_force<W>(g, z, sig, sh.px, sh.py, sh.pq, fax, fay, faz);
         const R ax = R(fax), ay = R(fay), az = R(faz);
         R dr = 0, jx = 0, jy = 0, jz = 0;
+        if constexpr (REC) {
+            // the moments the forward step computed from this state
+            const size_t e = (size_t)z * g.P;
+            if (check_ok(g.check, e + k < (size_t)g.pstride, CHK_LOAD)) {
+                dr = R(rec[e]);
+                jx = R(rec[e + g.pstride]);
+                jy = R(rec[e + 2 * (size_t)g.pstride]);
+                jz = R(rec[e + 3 * (size_t)g.pstride]);
+            }
+        } else {
+            W v[27];
+            pull_opaque<true>(p);
+            gather<T, FORM_S, WALL>(p, (unsigned)z * rowb, (unsigned)zm * rowb, (unsigned)zp * rowb, v);
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const R vi = R(v[i]);
-            dr += vi;
-            jx += R(CX(i)) * vi;
-            jy += R(CY(i)) * vi;
-            jz += R(CZ(i)) * vi;
+            for (int i = 0; i < 27; ++i) {
+                const R vi = R(v[i]);
+                dr += vi;
+                jx += R(CX(i)) * vi;
+                jy += R(CY(i)) * vi;
+                jz += R(CZ(i)) * vi;
+            }
         }
         const R rho = R(1) + dr;
         const R inv = R(1) / rho;
@@ -346,25 +365,34 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ acc,
     if (threadIdx.x == 0) grad[(size_t)b * nq + q] = base[(size_t)b * nq + q] + lds[0];
 }
 
-template <typename T, typename R>
+template <typename T, typename R, bool REC>
 static void adjoint_wall(const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s)
 {
     const dim3 grid((unsigned)(t.count() * t.nb));
     if (g.bcoef)
-        hipLaunchKernelGGL((k_adjoint<T, R, 256, true>), grid, dim3(256), 0, s, g, t, a);
+        hipLaunchKernelGGL((k_adjoint<T, R, 256, true, REC>), grid, dim3(256), 0, s, g, t, a);
     else
-        hipLaunchKernelGGL((k_adjoint<T, R, 256, false>), grid, dim3(256), 0, s, g, t, a);
+        hipLaunchKernelGGL((k_adjoint<T, R, 256, false, REC>), grid, dim3(256), 0, s, g, t, a);
+}
+
+template <typename T, typename R>
+static void adjoint_source(const Geom &g, const Tiles &t, const AdjointArgs &a, hipStream_t s)
+{
+    if (a.rec)
+        adjoint_wall<T, R, true>(g, t, a, s);
+    else
+        adjoint_wall<T, R, false>(g, t, a, s);
 }
 
 hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
                           hipStream_t s)
 {
     if (storage == 2)  // FP64 forward: FP64 adjoint
-        adjoint_wall<double, double>(g, t, a, s);
+        adjoint_source<double, double>(g, t, a, s);
     else if (precision == 2)
-        storage == 1 ? adjoint_wall<__half, double>(g, t, a, s) : adjoint_wall<float, double>(g, t, a, s);
+        storage == 1 ? adjoint_source<__half, double>(g, t, a, s) : adjoint_source<float, double>(g, t, a, s);
     else
-        storage == 1 ? adjoint_wall<__half, float>(g, t, a, s) : adjoint_wall<float, float>(g, t, a, s);
+        storage == 1 ? adjoint_source<__half, float>(g, t, a, s) : adjoint_source<float, float>(g, t, a, s);
     return hipGetLastError();
 }
 
@@ -382,6 +410,48 @@ hipError_t launch_project_grad(const Geom &g, const double *acc, const double *m
 {
     hipLaunchKernelGGL(k_project, dim3((unsigned)(g.B * nq)), dim3(256), 0, s, acc, modes, nq, g.P, g.ncol, base, grad);
     return hipGetLastError();
+}
+
+// One step of the two-buffer pattern (the step kernel's gather, collision and
+// store, so the state equals lbm_step's bitwise) that also records the
+// moments of the state it consumes for the adjoint (see step_tile).
+template <typename T, int BLOCK, bool WALL>
+__global__ __launch_bounds__(BLOCK) void k_step_record(const Geom g, const Tiles t, const T *__restrict__ src,
+                                                       T *__restrict__ dst, int step_off,
+                                                       typename RealOf<T>::type *__restrict__ rec)
+{
+    __shared__ float lref[href_lds_floats<T, BLOCK>()];
+    const TileCoord tc = decode_tile(t, BLOCK);
+    if (tc.k >= g.ncol) return;
+    step_tile<T, STEP_AB, WALL, KIND_MRT6, true>(g, t, tc, src, dst, *g.step_dev + step_off,
+                                                 lref + 27 * threadIdx.x, rec);
+}
+
+template <typename T>
+static hipError_t step_record_t(const Geom &g, const Tiles &t, const void *src, void *dst, int off, void *rec,
+                                hipStream_t s)
+{
+    using W = typename RealOf<T>::type;
+    // the step's tiles and tile order, 256 columns wide
+    Tiles tr = t;
+    tr.block = 256;
+    tr.nkb = (g.ncol + 255) / 256;
+    const dim3 grid((unsigned)(tr.count() * tr.nb));
+    if (g.bcoef)
+        hipLaunchKernelGGL((k_step_record<T, 256, true>), grid, dim3(256), 0, s, g, tr, (const T *)src, (T *)dst, off,
+                           (W *)rec);
+    else
+        hipLaunchKernelGGL((k_step_record<T, 256, false>), grid, dim3(256), 0, s, g, tr, (const T *)src, (T *)dst,
+                           off, (W *)rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_record(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int off,
+                              void *rec, hipStream_t s)
+{
+    if (storage == 2) return step_record_t<double>(g, t, src, dst, off, rec, s);
+    return storage == 1 ? step_record_t<__half>(g, t, src, dst, off, rec, s)
+                        : step_record_t<float>(g, t, src, dst, off, rec, s);
 }
 
 }  // namespace lbm

@@ -152,7 +152,8 @@ hipError_t static_scratch(double **out);
 
 // adjoint
 struct AdjointArgs {
-    const void *state;     // saved forward state holding S^T f^c
+    const void *state;     // saved forward state holding S^T f^c (or:)
+    const void *rec;       // the moments (rho - 1, j) of f^c recorded by the recording step
     const void *lam_in;    // lambda^{c+1} (stored plainly: lambda_i at its own node), float or double
     void *lam_out;         // lambda^c
     double *grad_part;     // [B][nzc][P][3]: FP64 per-column force sensitivities
@@ -163,6 +164,10 @@ struct AdjointArgs {
 };
 hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles &t, const AdjointArgs &a,
                           hipStream_t s);
+// one two-buffer step src -> dst that also records the moments of the state
+// it consumes into rec ([B][4][population stride] of the arithmetic type)
+hipError_t launch_step_record(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
+                              void *rec, hipStream_t s);
 // acc[b][k] += sigma * column sums of the step's gradient partials
 hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
                                   hipStream_t s);

@@ -55,6 +55,7 @@ struct Layout {
     int nt2 = 0;                   // its tiles
     size_t elem = 4;               // bytes per stored population
     size_t state_bytes = 0;
+    size_t record_bytes = 0;       // one moment record of the recording step (all pipes)
     // workspace offsets
     size_t off_state[2], off_box, off_nbr, off_bcoef, off_colxy, off_fshape, off_ztab, off_sigma, off_u0, off_step, off_step2, off_bar;
     size_t off_check = 0;  // bounds-violation flags of a checked build (one word)
@@ -182,6 +183,7 @@ int build_layout(const lbm_config *cfg, Layout &L)
     }
     const long long pipe_elems = 27 * L.pstride;
     L.state_bytes = align_up((size_t)pipe_elems * c.batch * L.elem, 256);
+    L.record_bytes = align_up((size_t)4 * L.pstride * c.batch * (c.storage == 2 ? 8 : 4), 256);
     if (c.xcd_remap < 0 || c.xcd_remap > 4096) return bad("xcd_remap must be in 0..4096");
     L.step = Tiles{block, zchunk, (L.ncol + block - 1) / block, (c.nz + zchunk - 1) / zchunk, c.xcd_remap, 0, c.batch};
     L.obs = Tiles{256, kObsZChunk, (L.ncol + 255) / 256, (c.nz + kObsZChunk - 1) / kObsZChunk, 1, 0, c.batch};
@@ -501,6 +503,7 @@ int lbm_describe(const lbm_config *cfg, lbm_layout *out)
         out->workspace_bytes = (int64_t)L.total;
         out->bytes_per_update = 2 * 27 * (int64_t)L.elem;
         out->population_stride = L.pstride;
+        out->record_bytes = (int64_t)L.record_bytes;
     }
     return LBM_OK;
 }
@@ -1012,6 +1015,38 @@ int lbm_recompute(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *ri
     return LBM_OK;
 }
 
+int lbm_recompute_moments(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *scratch, size_t stride,
+                          void *records, size_t record_stride)
+{
+    CHECK_CTX(c);
+    if (!start || !scratch || !records || n < 1 || s0 < 0)
+        return fail(c, LBM_EINVAL, "lbm_recompute_moments: bad arguments");
+    if (c->cfg.pattern != 0) return fail(c, LBM_EINVAL, "lbm_recompute_moments needs the two-buffer pattern");
+    if (c->cfg.collision != 0 || c->cfg.equilibrium != 0)
+        return fail(c, LBM_EINVAL, "lbm_recompute_moments: the paper's scheme only (collision = equilibrium = 0)");
+    if (stride < c->L.state_bytes || (stride & 255) || ((uintptr_t)scratch & 255) ||
+        record_stride < c->L.record_bytes || (record_stride & 255) || ((uintptr_t)records & 255))
+        return fail(c, LBM_EINVAL, "lbm_recompute_moments: strides below the state / record size or not 256-byte "
+                                   "aligned");
+    const char *st = (const char *)start;
+    char *s = (char *)scratch, *r = (char *)records;
+    // start is scratch state 0 itself or lies outside both scratch states
+    const size_t sb = c->L.state_bytes;
+    if (st != s && st < s + stride + sb && st + sb > s)
+        return fail(c, LBM_EINVAL, "lbm_recompute_moments: start overlaps the scratch states");
+    if (st != s) HIPCHK(c, hipMemcpyAsync(s, start, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    Geom g = c->geom;
+    g.step_dev = (const long long *)(c->ws + c->L.off_step2);
+    HIPCHK(c, launch_set_step((long long *)(c->ws + c->L.off_step2), s0, 0, c->stream));
+    Tiles t = c->L.step;
+    t.b0 = 0;
+    t.nb = c->cfg.batch;
+    for (int j = 0; j < n; ++j)
+        HIPCHK(c, launch_step_record(c->cfg.storage, g, t, s + (size_t)(j & 1) * stride,
+                                     s + (size_t)((j + 1) & 1) * stride, j, r + (size_t)j * record_stride, c->stream));
+    return LBM_OK;
+}
+
 int lbm_profile_accumulate(lbm_ctx *c)
 {
     CHECK_CTX(c);
@@ -1095,13 +1130,27 @@ int lbm_adjoint_reset(lbm_ctx *c, int64_t obs_begin, int64_t obs_end)
     return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state_stride, double *grad)
+// n reverse steps from saved states (records == false) or moment records
+static int adjoint_sweep(lbm_ctx *c, int32_t n, const void *fwd, size_t stride, bool records, double *grad)
 {
-    CHECK_CTX(c);
-    if (!c->cfg.adjoint || !c->adj_ready) return fail(c, LBM_ESTATE, "lbm_adjoint_step before lbm_adjoint_reset");
-    if (n < 1 || !fwd_states || (c->cfg.n_modes > 0 && !grad)) return fail(c, LBM_EINVAL, "lbm_adjoint_step: bad arguments");
-    if (c->cursor - n + 1 < 0) return fail(c, LBM_ESTATE, "lbm_adjoint_step: cursor would move below 0");
-    if (state_stride < c->L.state_bytes) return fail(c, LBM_EINVAL, "lbm_adjoint_step: state_stride < state size");
+    const char *name = records ? "lbm_adjoint_step_moments" : "lbm_adjoint_step";
+    char msg[160];
+    if (!c->cfg.adjoint || !c->adj_ready) {
+        std::snprintf(msg, sizeof msg, "%s before lbm_adjoint_reset", name);
+        return fail(c, LBM_ESTATE, msg);
+    }
+    if (n < 1 || !fwd || (c->cfg.n_modes > 0 && !grad)) {
+        std::snprintf(msg, sizeof msg, "%s: bad arguments", name);
+        return fail(c, LBM_EINVAL, msg);
+    }
+    if (c->cursor - n + 1 < 0) {
+        std::snprintf(msg, sizeof msg, "%s: cursor would move below 0", name);
+        return fail(c, LBM_ESTATE, msg);
+    }
+    if (stride < (records ? c->L.record_bytes : c->L.state_bytes)) {
+        std::snprintf(msg, sizeof msg, "%s: stride < %s size", name, records ? "record" : "state");
+        return fail(c, LBM_EINVAL, msg);
+    }
     const int nq = 2 * c->cfg.n_modes;
     const double wgt = 1.0 / ((double)(c->obs_end - c->obs_begin) * (double)c->L.ncol * c->cfg.nz);
     double *acc = (double *)(c->ws + c->L.off_grad_col), *base = (double *)(c->ws + c->L.off_grad_base);
@@ -1112,7 +1161,7 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
     }
     for (int j = n - 1; j >= 0; --j) {
         AdjointArgs a{};
-        a.state = (const char *)fwd_states + (size_t)j * state_stride;
+        (records ? a.rec : a.state) = (const char *)fwd + (size_t)j * stride;
         a.lam_in = c->ws + c->L.off_lam[c->lam_cur];
         a.lam_out = c->ws + c->L.off_lam[c->lam_cur ^ 1];
         a.grad_part = (double *)(c->ws + c->L.off_grad_part);
@@ -1133,6 +1182,18 @@ int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state
     if (nq > 0)
         HIPCHK(c, launch_project_grad(c->geom, acc, (const double *)(c->ws + c->L.off_modes), nq, base, grad, c->stream));
     return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, int32_t n, const void *fwd_states, size_t state_stride, double *grad)
+{
+    CHECK_CTX(c);
+    return adjoint_sweep(c, n, fwd_states, state_stride, false, grad);
+}
+
+int lbm_adjoint_step_moments(lbm_ctx *c, int32_t n, const void *records, size_t record_stride, double *grad)
+{
+    CHECK_CTX(c);
+    return adjoint_sweep(c, n, records, record_stride, true, grad);
 }
 
 int lbm_ring_sample(lbm_ctx *c, double r0, int32_t ntheta, float *ring)

@@ -56,9 +56,14 @@ enum StepMode : int { STEP_AB = 0, STEP_AA_EVEN = 1, STEP_AA_ODD = 2 };
 // g(n) (streaming + bounce-back), collision at a(x, n), store of g*(n).
 // For the AA modes src and dst are the same buffer.
 // lref: FP16 storage, this thread's 27 floats of LDS for its column references
-template <typename T, int MODE, bool WALL = false, int KIND = KIND_MRT6>
+// REC: also record the moments (rho - 1, j_x, j_y, j_z) of the gathered
+// state g(n) into rec[b][q][z P + k] (q = 0..3, each q a region of one
+// population stride), in the collision's arithmetic type: the discrete
+// adjoint needs the forward state only through them
+template <typename T, int MODE, bool WALL = false, int KIND = KIND_MRT6, bool REC = false>
 __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const TileCoord &tc, const T *src, T *dst,
-                                          long long n, float *lref = nullptr)
+                                          long long n, float *lref = nullptr,
+                                          typename RealOf<T>::type *rec = nullptr)
 {
     const int k = tc.k;
     Pull<T, WALL> p =
@@ -78,6 +83,16 @@ __device__ __forceinline__ void step_tile(const Geom &g, const Tiles &t, const T
         typename RealOf<T>::type v[27];
         pull_opaque<WALL || MODE == STEP_AA_ODD>(p);  // FP16 (see there)
         gather<T, FORM, WALL>(p, zo, zmo, zpo, v);
+        if constexpr (REC) {
+            const Moments<typename RealOf<T>::type> m = moments_of(v);
+            if (p.ok_store(zo + p.own)) {
+                const size_t e = (size_t)tc.b * 4 * g.pstride + (size_t)z * g.P + k;
+                __builtin_nontemporal_store(m.dr, rec + e);
+                __builtin_nontemporal_store(m.jx, rec + e + g.pstride);
+                __builtin_nontemporal_store(m.jy, rec + e + 2 * (size_t)g.pstride);
+                __builtin_nontemporal_store(m.jz, rec + e + 3 * (size_t)g.pstride);
+            }
+        }
         collide<T, KIND>(g, v, sig, sh, z);
         if constexpr (MODE == STEP_AB)
             store_all<T>(pout, p, zo + p.own, v);

@@ -176,6 +176,20 @@ class Pipe:
         self._check(self.lib.lbm_recompute(self._ctx, C.c_void_p(_ptr(start)), int(s0), int(n),
                                            C.c_void_p(_ptr(ring)), C.c_size_t(stride)), "lbm_recompute")
 
+    def recompute_moments(self, start: torch.Tensor, s0: int, scratch: torch.Tensor, records: torch.Tensor,
+                          n: int | None = None):
+        """scratch[0] := start (state of step s0), then n steps alternating
+        between the two scratch states, recording the moments (rho - 1, j) of
+        each consumed state into records[j]; the context's own state is
+        untouched."""
+        n = records.shape[0] if n is None else n
+        stride = scratch.stride(0) * scratch.element_size()
+        rstride = records.stride(0) * records.element_size()
+        self._check(self.lib.lbm_recompute_moments(self._ctx, C.c_void_p(_ptr(start)), int(s0), int(n),
+                                                   C.c_void_p(_ptr(scratch)), C.c_size_t(stride),
+                                                   C.c_void_p(_ptr(records)), C.c_size_t(rstride)),
+                    "lbm_recompute_moments")
+
     def profile_accumulate(self):
         self._check(self.lib.lbm_profile_accumulate(self._ctx), "lbm_profile_accumulate")
 
@@ -217,6 +231,11 @@ class Pipe:
         self._check(self.lib.lbm_state_bytes(self._ctx, C.byref(v)), "lbm_state_bytes")
         return int(v.value)
 
+    @property
+    def record_bytes(self) -> int:
+        """Bytes of one moment record of :meth:`recompute_moments`."""
+        return int(self.layout.record_bytes)
+
     def save(self, out: torch.Tensor | None = None) -> tuple[torch.Tensor, int]:
         if out is None:
             out = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
@@ -237,6 +256,15 @@ class Pipe:
         stride = states.stride(0) * states.element_size()
         self._check(self.lib.lbm_adjoint_step(self._ctx, int(n), C.c_void_p(_ptr(states)), C.c_size_t(stride),
                                               C.c_void_p(_ptr(grad))), "lbm_adjoint_step")
+
+    def adjoint_step_moments(self, records: torch.Tensor, grad: torch.Tensor, n: int | None = None):
+        """Consume moment ``records`` ([n][record_bytes] uint8, forward order,
+        from :meth:`recompute_moments`) last to first."""
+        n = records.shape[0] if n is None else n
+        stride = records.stride(0) * records.element_size()
+        self._check(self.lib.lbm_adjoint_step_moments(self._ctx, int(n), C.c_void_p(_ptr(records)),
+                                                      C.c_size_t(stride), C.c_void_p(_ptr(grad))),
+                    "lbm_adjoint_step_moments")
 
 
 def radial_profiles(acc: np.ndarray, cfg: dict, bin_width: float = 1.0):

@@ -146,3 +146,87 @@ def test_adjoint_matches_central_differences(gpu):
         rel[frac] = np.linalg.norm(g - fd) / np.linalg.norm(fd)
         _log(f"eps = {frac:g} * max|amps|: |g - g_fd| / |g_fd| = {rel[frac]:.3e}")
     assert min(rel.values()) < 1e-4
+
+
+@pytest.mark.parametrize("storage,wall", [(0, 0), (1, 0), (2, 0), (0, 1)])
+def test_recompute_moments_steps_and_records(gpu, storage, wall):
+    """lbm_recompute_moments: the states it steps through equal
+    lbm_recompute's bitwise (compared as exported populations: the padding of
+    a saved state is never written by a step), and the moments it records of
+    each state sum to that state's FP64 mass and momentum (lbm_diagnostics, a
+    separate reduction of the populations)."""
+    import paper_2405_12082_amd as P
+    cfg = dict(TINY, storage=storage, wall=wall)
+    p = P.Pipe(cfg, TINY_AMPS[None])
+    p.step(5)
+    start, s0 = p.save()
+    n = 4
+    ring = torch.empty((n + 1, p.state_bytes), dtype=torch.uint8, device="cuda")
+    p.recompute(start, s0, ring)
+    scratch = torch.empty((2, p.state_bytes), dtype=torch.uint8, device="cuda")
+    rec = torch.empty((n, p.record_bytes), dtype=torch.uint8, device="cuda")
+    p.recompute_moments(start, s0, scratch, rec)
+
+    def pops(blob, step):
+        p.load(blob, step)
+        return p.populations().clone()
+    for j in (n - 1, n):
+        assert torch.equal(pops(scratch[j & 1], s0 + j), pops(ring[j], s0 + j)), j
+    lay = p.layout
+    ncol, pitch, ps, nz = int(lay.n_fluid_columns), int(lay.plane_pitch), int(lay.population_stride), cfg["nz"]
+    dt = np.float64 if storage == 2 else np.float32
+    nf = ncol * nz
+    for j in range(n):
+        p.load(ring[j], s0 + j)
+        d = p.diagnostics()[0]
+        r = rec[j].cpu().numpy().view(dt)[:4 * ps].reshape(4, ps)[:, :nz * pitch].reshape(4, nz, pitch)[:, :, :ncol]
+        sums = r.astype(np.float64).sum(axis=(1, 2))
+        ref = np.array([d[0] - nf, d[1], d[2], d[3]])
+        # per-node moments rounded once in FP32 (FP64 storage: FP64)
+        tol = (1e-13 if storage == 2 else 1e-6) * (np.abs(r).max() * nf)
+        _log(f"storage {storage} wall {wall} state {j}: record sums - FP64 sums {np.abs(sums - ref).max():.3e} "
+             f"(bound {tol:.3e})")
+        assert np.all(np.abs(sums - ref) <= tol)
+    p.close()
+
+
+@pytest.mark.parametrize("storage,wall,precision,tol", [(0, 0, "fp32", 1e-6), (0, 1, "fp32", 1e-6),
+                                                        (1, 0, "fp32", 1e-6), (2, 0, "fp64", 1e-12),
+                                                        (2, 1, "fp64", 1e-12)])
+def test_moment_and_state_records_give_the_same_gradient(gpu, storage, wall, precision, tol):
+    """The reverse sweep from moment records against the sweep from whole
+    saved states: the only difference is the forward moments, rounded once
+    in the collision's arithmetic type against FP64 sums of the gathered
+    state (FP64 storage: FP64 either way, summed in another order)."""
+    cfg = dict(TINY, wall=wall, storage=storage)
+    g = {}
+    for rec in ("moments", "states"):
+        run = gpu.EnergyAdjoint(cfg, 20, 40, checkpoint_every=7, precision=precision, records=rec)
+        g[rec] = run.gradient(TINY_AMPS[None])[1][0]
+    err = np.abs(g["moments"] - g["states"]).max() / np.abs(g["states"]).max()
+    _log(f"storage {storage} wall {wall}: moment records vs state records {err:.3e}")
+    assert err < tol
+
+
+def test_recompute_moments_rejects_bad_arguments(gpu):
+    import paper_2405_12082_amd as P
+    p = P.Pipe(TINY, TINY_AMPS[None])
+    start, s0 = p.save()
+    sb, rb = p.state_bytes, p.record_bytes
+    scratch = torch.empty((2, sb), dtype=torch.uint8, device="cuda")
+    rec = torch.empty((2, rb), dtype=torch.uint8, device="cuda")
+    bad_scratch = torch.empty((2, sb + 64), dtype=torch.uint8, device="cuda")  # stride not a multiple of 256
+    with pytest.raises(RuntimeError, match="lbm_recompute_moments"):
+        p.recompute_moments(start, s0, bad_scratch, rec)
+    short = torch.empty((2, rb - 256), dtype=torch.uint8, device="cuda")  # record stride below the record size
+    with pytest.raises(RuntimeError, match="lbm_recompute_moments"):
+        p.recompute_moments(start, s0, scratch, short)
+    with pytest.raises(RuntimeError, match="lbm_recompute_moments"):
+        p.recompute_moments(scratch[1], s0, scratch, rec)  # start inside the second scratch state
+    with pytest.raises(RuntimeError, match="lbm_adjoint_step_moments"):
+        p.adjoint_step_moments(rec, torch.zeros((1, 4), dtype=torch.float64, device="cuda"))  # no adjoint buffers
+    p.close()
+    aa = P.Pipe(dict(TINY, pattern=1), TINY_AMPS[None])
+    with pytest.raises(RuntimeError, match="two-buffer"):
+        aa.recompute_moments(aa.save()[0], 0, scratch, rec)
+    aa.close()
