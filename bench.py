@@ -409,7 +409,8 @@ def leg_adjoint(fd_frac=1e-2):
     every 100; gradient of the streamwise energy over steps 1501..2000 with
     respect to the 12 trigger amplitudes, by the FP32 forward with the
     adjoint state stored in FP32 (the bench's path) and in FP64, FP64
-    vector-Jacobian arithmetic in both.  Cost ratio = (recompute + adjoint
+    vector-Jacobian arithmetic in both, the recompute keeping the moments
+    (rho - 1, j) of each forward state.  Cost ratio = (recompute + adjoint
     sweep) / plain forward over the same steps.  Accuracy: relative L2
     distance to central differences (step 1% of the largest amplitude) of
     the FP64-storage forward."""
@@ -456,7 +457,7 @@ def leg_adjoint(fd_frac=1e-2):
         out[f"adjoint_state_{prec}"]["rel_err_vs_central_differences"] = float(np.linalg.norm(g - fd) /
                                                                                np.linalg.norm(fd))
     out.update({"forward_plain_ms": round(ms_fwd, 2), "fluid_nodes": nf, "adjoint_state": "fp32",
-                "adjoint_arithmetic": "fp64",
+                "adjoint_arithmetic": "fp64", "recompute_records": "moments (rho - 1, j)",
                 "adjoint_fwd_cost_ratio": out["adjoint_state_fp32"]["cost_ratio"],
                 "grad_norm": float(np.linalg.norm(grads["fp32"])),
                 "central_differences": {"forward": "fp64 storage", "step": f"{fd_frac:g} * max|amps|"}})
