@@ -7,7 +7,11 @@
 // C depends on f only through rho, j and the stress moments m_4..m_8, so the
 // vector-Jacobian product is the chain rule through these 9 moments, derived
 // by hand from the collision of the forward kernel (deviation form of the
-// Hermite-6 equilibrium, Guo forcing, relaxation of m_4..8 with omega).
+// Hermite-6 equilibrium, Guo forcing, relaxation of m_4..8 with omega).  The
+// stress moments enter C linearly with constant coefficients, so dC/df
+// depends on f only through rho and j: the reverse step reads them from a
+// moment record of the recompute (k_step_record below) or sums them from a
+// saved state.
 // The force sensitivities are accumulated per column in FP64 and projected
 // onto the trigger-force mode shapes of Eq. (TurbForce).
 #include "lbm_device.h"
@@ -17,9 +21,10 @@
 namespace lbm {
 
 // The adjoint state is stored as S (float or double); the vector-Jacobian
-// arithmetic is FP64 (R) for either: the forward state is decoded as in the
-// forward kernel and promoted, the adjoint state promoted on load and rounded
-// to S on store.  (With FP32 arithmetic the gradient of the 2000-step
+// arithmetic is FP64 (R) for either: the forward moments (recorded in the
+// forward's arithmetic type, or summed from the saved state decoded as in
+// the forward kernel) are promoted, the adjoint state promoted on load and
+// rounded to S on store.  (With FP32 arithmetic the gradient of the 2000-step
 // adjoint workload is 1.4e-4 from central differences; with FP64 arithmetic
 // it is 3.6e-5 whether the state is stored in FP32 or FP64.)
 
