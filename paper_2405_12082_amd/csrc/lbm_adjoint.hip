@@ -313,22 +313,28 @@ __global__ __launch_bounds__(BLOCK) LBM_ADJ_OCCUPANCY void k_adjoint(const Geom 
         G[1] += cz * (double)sy;
         G[2] += sz * (double)sz_;
     }
-    double *gp = a.grad_part + (((size_t)b * t.nzc + zc) * g.P + k) * 3;
-    gp[0] = G[0];
-    gp[1] = G[1];
-    gp[2] = G[2];
+    // accumulated over the steps of the sweep with sigma(c), the time factor
+    // of this step's trigger force (each slot belongs to one thread, and the
+    // steps run in order, so the sums are deterministic)
+    const double sd = (double)sig;
+    if (sd != 0.0) {
+        double *gp = a.grad_part + (((size_t)b * t.nzc + zc) * g.P + k) * 3;
+        gp[0] += sd * G[0];
+        gp[1] += sd * G[1];
+        gp[2] += sd * G[2];
+    }
 }
 
-// acc[b][k] += sigma(n) * (sum over the z-chunks of step n's column partials):
-// the force sensitivity of every column, summed over the steps of the sweep
-// so far.  The partials of one (pipe, z-chunk) are 3 P consecutive doubles;
-// a block takes 64 of them (one per lane), its 16 waves sum every 16th
-// z-chunk each, and wave 0 adds the 16 wave sums in a fixed order
-// (deterministic).
+// acc[b][k] = sum over the z-chunks of the column partials (each the sum
+// over the sweep's steps so far of sigma(n) times the step's sensitivities):
+// the force sensitivity of every column.  The partials of one (pipe,
+// z-chunk) are 3 P consecutive doubles; a block takes 64 of them (one per
+// lane), its 16 waves sum every 16th z-chunk each, and wave 0 adds the 16
+// wave sums in a fixed order (deterministic).
 constexpr int kAccWaves = 16;
 __global__ __launch_bounds__(64 * kAccWaves) void k_grad_accumulate(const double *__restrict__ part,
                                                                     double *__restrict__ acc, int nzc, int P,
-                                                                    int ncol, int blocks_per_pipe, double sigma)
+                                                                    int ncol, int blocks_per_pipe)
 {
     __shared__ double red[kAccWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(64 * kAccWaves) void k_grad_accumulate(const double
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < kAccWaves; ++q) t += red[q][lane];
-        acc[(size_t)b * 3 * P + e] += sigma * t;
+        acc[(size_t)b * 3 * P + e] = t;
     }
 }
 
@@ -401,12 +407,11 @@ hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles
     return hipGetLastError();
 }
 
-hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
-                                  hipStream_t s)
+hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, hipStream_t s)
 {
     const int per_pipe = (3 * g.ncol + 63) / 64;
     hipLaunchKernelGGL(k_grad_accumulate, dim3((unsigned)(per_pipe * g.B)), dim3(64 * kAccWaves), 0, s, grad_part, acc,
-                       t.nzc, g.P, g.ncol, per_pipe, sigma);
+                       t.nzc, g.P, g.ncol, per_pipe);
     return hipGetLastError();
 }
 

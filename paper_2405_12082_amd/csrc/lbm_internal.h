@@ -156,7 +156,7 @@ struct AdjointArgs {
     const void *rec;       // the moments (rho - 1, j) of f^c recorded by the recording step
     const void *lam_in;    // lambda^{c+1} (stored plainly: lambda_i at its own node), float or double
     void *lam_out;         // lambda^c
-    double *grad_part;     // [B][nzc][P][3]: FP64 per-column force sensitivities
+    double *grad_part;     // [B][nzc][P][3]: FP64 per-column force sensitivities times sigma, summed over the steps
     long long cursor;      // c
     int in_window;         // c in [obs_begin, obs_end)
     int has_next;          // c + 1 was collided (lambda^{c+1} nonzero)
@@ -168,9 +168,8 @@ hipError_t launch_adjoint(int storage, int precision, const Geom &g, const Tiles
 // it consumes into rec ([B][4][population stride] of the arithmetic type)
 hipError_t launch_step_record(int storage, const Geom &g, const Tiles &t, const void *src, void *dst, int step_off,
                               void *rec, hipStream_t s);
-// acc[b][k] += sigma * column sums of the step's gradient partials
-hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, double sigma,
-                                  hipStream_t s);
+// acc[b][k] = the column sums over the z-chunks of the gradient partials
+hipError_t launch_grad_accumulate(const Geom &g, const Tiles &t, const double *grad_part, double *acc, hipStream_t s);
 // grad[b][q] = base[b][q] + sum_k acc[b][k] . shape_q(k)
 hipError_t launch_project_grad(const Geom &g, const double *acc, const double *modes, int nq, const double *base,
                                double *grad, hipStream_t s);

@@ -1126,6 +1126,8 @@ int lbm_adjoint_reset(lbm_ctx *c, int64_t obs_begin, int64_t obs_end)
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[0], lam, c->stream));
     HIPCHK(c, launch_fill(c->ws + c->L.off_lam[1], lam, c->stream));
     HIPCHK(c, launch_fill(c->ws + c->L.off_grad_col, (size_t)c->cfg.batch * c->L.P * 3 * sizeof(double), c->stream));
+    HIPCHK(c, launch_fill(c->ws + c->L.off_grad_part, (size_t)c->cfg.batch * c->L.adj.nzc * c->L.P * 3 * sizeof(double),
+                          c->stream));
     c->grad_base_set = false;
     return LBM_OK;
 }
@@ -1169,18 +1171,16 @@ static int adjoint_sweep(lbm_ctx *c, int32_t n, const void *fwd, size_t stride, 
         a.in_window = c->cursor >= c->obs_begin && c->cursor < c->obs_end;
         a.has_next = c->cursor + 1 < c->obs_end;
         a.energy_weight = wgt;
+        // (the kernel adds sigma(c) times its sensitivities to the partials)
         HIPCHK(c, launch_adjoint(c->cfg.storage, c->cfg.adjoint, c->geom, c->L.adj, a, c->stream));
-        if (nq > 0) {
-            const double sig = (c->cursor < c->L.n_sigma) ? std::sin(2.0 * M_PI * (double)c->cursor / c->cfg.period) : 0.0;
-            // the forward used the FP32 table value of sigma (FP64 storage: the FP64 one); the same here
-            const double sigf = c->cfg.storage == 2 ? sig : (double)(float)sig;
-            if (sigf != 0.0) HIPCHK(c, launch_grad_accumulate(c->geom, c->L.adj, a.grad_part, acc, sigf, c->stream));
-        }
         c->lam_cur ^= 1;
         c->cursor -= 1;
     }
-    if (nq > 0)
+    if (nq > 0) {
+        HIPCHK(c, launch_grad_accumulate(c->geom, c->L.adj, (const double *)(c->ws + c->L.off_grad_part), acc,
+                                         c->stream));
         HIPCHK(c, launch_project_grad(c->geom, acc, (const double *)(c->ws + c->L.off_modes), nq, base, grad, c->stream));
+    }
     return LBM_OK;
 }
 
