@@ -407,7 +407,9 @@ def elementwise_add_rate(gib=4, reps=20):
 def leg_adjoint(fd_frac=1e-2):
     """Adjoint workload: 96x96x384 pipe (R = 45), 2000 steps, checkpoints
     every 100; gradient of the streamwise energy over steps 1501..2000 with
-    respect to the 12 trigger amplitudes, by the FP32 forward with the
+    respect to the 12 trigger amplitudes (gradient_cost_ratio: the whole
+    gradient, forward with checkpoints and energy sampling plus the reverse
+    sweep, over one plain forward), by the FP32 forward with the
     adjoint state stored in FP32 (the bench's path) and in FP64, FP64
     vector-Jacobian arithmetic in both, the recompute keeping the moments
     (rho - 1, j) of each forward state.  Cost ratio = (recompute + adjoint
@@ -440,7 +442,9 @@ def leg_adjoint(fd_frac=1e-2):
             grads[prec] = g[0]
             out[f"adjoint_state_{prec}"] = {"backward_ms": round(t["backward_ms"], 2),
                                             "forward_with_checkpoints_ms": round(t["forward_ms"], 2),
-                                            "cost_ratio": round(t["backward_ms"] / ms_fwd, 3), "J": float(J[0])}
+                                            "cost_ratio": round(t["backward_ms"] / ms_fwd, 3),
+                                            "gradient_cost_ratio": round((t["forward_ms"] + t["backward_ms"]) / ms_fwd, 3),
+                                            "J": float(J[0])}
             del run
             torch.cuda.empty_cache()
         ref = EnergyAdjoint(dict(cfg, storage=2), b, e, checkpoint_every=C, stream=stream, precision="fp64")
