@@ -160,6 +160,12 @@ int main(void)
     if (lbm_set_watchdog(NULL, 1e-6) != LBM_EINVAL) return 15;
     if (lbm_get_step(NULL, NULL) != LBM_EINVAL) return 16;
     if (lbm_ring_spectrum_static(NULL, 1, 1, 64, 4, NULL, NULL, NULL, NULL) != LBM_EINVAL) return 17;
+    if (lbm_recompute_moments(NULL, NULL, 0, 1, NULL, 0, NULL, 0) != LBM_EINVAL) return 19;
+    if (lbm_adjoint_step_moments(NULL, 1, NULL, 0, NULL) != LBM_EINVAL) return 20;
+    lbm_config r = base();
+    r.adjoint = 1;
+    lbm_layout rl;
+    if (lbm_describe(&r, &rl) != LBM_OK || rl.record_bytes < 4 * 4 * rl.n_fluid_nodes * r.batch) return 21;
     printf("%d %d\n", valid, invalid);
     return valid > 0 && invalid > 0 ? 0 : 18;
 }
