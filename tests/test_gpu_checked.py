@@ -6,7 +6,8 @@ load and store of the gather and store paths, every neighbour-table entry
 and column index.  Run on every kernel path -- both patterns, both walls,
 the three storage forms, batched and persistent launches, graph replay, two
 steps per launch, the comparison schemes, the observers and the coherent-
-structure sampling, the adjoint with recomputation -- it records no
+structure sampling, the adjoint with recomputation (moment records and
+saved states, FP32 and FP16 forward) -- it records no
 violation, and its results equal the release build's bitwise (the tests
 change no arithmetic)."""
 import sys
