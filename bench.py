@@ -409,7 +409,9 @@ def leg_adjoint(fd_frac=1e-2):
     every 100; gradient of the streamwise energy over steps 1501..2000 with
     respect to the 12 trigger amplitudes (gradient_cost_ratio: the whole
     gradient, forward with checkpoints and energy sampling plus the reverse
-    sweep, over one plain forward), by the FP32 forward with the
+    sweep, over one plain forward; recorded_forward: the FP32-state gradient
+    with the moments of every forward state kept in device memory instead
+    of checkpoints, no recompute), by the FP32 forward with the
     adjoint state stored in FP32 (the bench's path) and in FP64, FP64
     vector-Jacobian arithmetic in both, the recompute keeping the moments
     (rho - 1, j) of each forward state.  Cost ratio = (recompute + adjoint
@@ -447,6 +449,20 @@ def leg_adjoint(fd_frac=1e-2):
                                             "J": float(J[0])}
             del run
             torch.cuda.empty_cache()
+        # the same gradient with the moments of every forward state kept in
+        # device memory (no recompute): the whole gradient's cost
+        run = EnergyAdjoint(cfg, b, e, stream=stream, precision="fp32", recompute=False)
+        run.gradient(amps)
+        J, g = run.gradient(amps)
+        t = dict(run.timing)
+        out["recorded_forward"] = {"backward_ms": round(t["backward_ms"], 2),
+                                   "forward_with_records_ms": round(t["forward_ms"], 2),
+                                   "cost_ratio": round(t["backward_ms"] / ms_fwd, 3),
+                                   "gradient_cost_ratio": round((t["forward_ms"] + t["backward_ms"]) / ms_fwd, 3),
+                                   "record_bytes": int(run.all_records.numel()),
+                                   "equals_checkpoint_and_recompute": bool(np.array_equal(g[0], grads["fp32"]))}
+        del run
+        torch.cuda.empty_cache()
         ref = EnergyAdjoint(dict(cfg, storage=2), b, e, checkpoint_every=C, stream=stream, precision="fp64")
         eps = fd_frac * np.abs(amps).max()
         fd = np.zeros_like(grads["fp32"])

@@ -115,6 +115,7 @@ def load(path):
         "lbm_recompute": ([vp, vp, i64, i32, vp, C.c_size_t], C.c_int),
         "lbm_recompute_moments": ([vp, vp, i64, i32, vp, C.c_size_t, vp, C.c_size_t], C.c_int),
         "lbm_adjoint_step_moments": ([vp, i32, vp, C.c_size_t, vp], C.c_int),
+        "lbm_step_recording": ([vp, i32, vp, C.c_size_t], C.c_int),
         "lbm_ring_sample": ([vp, C.c_double, i32, vp], C.c_int),
         "lbm_ring_spectrum": ([vp, vp, i32, i32, vp, vp, vp], C.c_int),
         "lbm_ring_spectrum_static": ([vp, i32, i32, i32, i32, vp, vp, vp, vp], C.c_int),

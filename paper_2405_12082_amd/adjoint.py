@@ -9,8 +9,12 @@ Eq. (TurbForce).
 
 Memory: forward saves a checkpoint every ``checkpoint_every`` steps; the
 reverse sweep restores one checkpoint at a time, recomputes its segment into
-a ring of saved states and runs the adjoint steps over it (checkpoint and
-recompute), so device memory is (N/C + C) states instead of N.
+a ring of records (the moments rho - 1 and j of each state, 16 B per node in
+FP32, or whole saved states) and runs the adjoint steps over it (checkpoint
+and recompute), so device memory is N/C states plus C records instead of N
+states.  With ``recompute=False`` the forward run records the moments of
+every state itself (N + 1 records, 78 GB for 2000 steps of a 96x96x384
+pipe) and the reverse sweep reads them without recomputing.
 """
 from __future__ import annotations
 
@@ -33,17 +37,24 @@ class EnergyAdjoint:
     records: what the recompute keeps of each forward state for the reverse
     steps: "moments" (default: rho - 1 and j, 16 B per node, the collision's
     Jacobian needs no more) or "states" (the whole saved state, 108 B).
+    recompute: False keeps the moment records of the whole forward run in
+    device memory instead of checkpoints (moment records only).
     """
 
     def __init__(self, cfg: dict, obs_begin: int, obs_end: int, checkpoint_every: int = 100,
-                 device="cuda", stream=None, precision: str = "fp32", library=None, records: str = "moments"):
+                 device="cuda", stream=None, precision: str = "fp32", library=None, records: str = "moments",
+                 recompute: bool = True):
         if not (0 <= obs_begin < obs_end):
             raise ValueError("need 0 <= obs_begin < obs_end")
         if precision not in ("fp32", "fp64"):
             raise ValueError("precision must be 'fp32' or 'fp64'")
         if records not in ("moments", "states"):
             raise ValueError("records must be 'moments' or 'states'")
+        if not recompute and records != "moments":
+            raise ValueError("recompute=False keeps moment records")
         self.records = records
+        self.recompute = bool(recompute)
+        self.all_records = None  # recompute=False: the forward run's records
         self.scratch = None
         self.cfg = dict(cfg, adjoint=2 if precision == "fp64" else 1)
         self.obs_begin, self.obs_end = int(obs_begin), int(obs_end)
@@ -71,6 +82,8 @@ class EnergyAdjoint:
         """Run the forward model and return J per pipe ([batch] FP64)."""
         p = self._new_pipe(amps)
         N = self.last_step
+        if keep_checkpoints and not self.recompute:
+            return self._objective_recording(p, N)
         if keep_checkpoints:
             nck = N // self.C + 1
             if self.ckpt is None or self.ckpt.shape != (nck, p.state_bytes):
@@ -83,6 +96,25 @@ class EnergyAdjoint:
                 p.energy_accumulate(acc)
             if n < N:
                 p.step(1)
+        return acc.cpu().numpy() / (self.obs_end - self.obs_begin)
+
+    def _objective_recording(self, p, N) -> np.ndarray:
+        """The forward run recording the moments of states 0..N (the last by
+        one more step, whose state is not used)."""
+        if self.all_records is None or self.all_records.shape != (N + 1, p.record_bytes):
+            self.all_records = None
+            self.all_records = torch.empty((N + 1, p.record_bytes), dtype=torch.uint8, device=self.device)
+        acc = torch.zeros(p.cfg.batch, dtype=torch.float64, device=self.device)
+        n = 0
+        while n <= N:
+            if self.obs_begin <= n:
+                p.energy_accumulate(acc)
+                k = 1
+            else:
+                k = self.obs_begin - n  # up to the window in one call
+            p.step_recording(self.all_records[n:n + k])
+            n += k
+        self.ckpt = self.all_records  # marks a recorded run for backward
         return acc.cpu().numpy() / (self.obs_end - self.obs_begin)
 
     def forward(self, amps) -> np.ndarray:
@@ -106,6 +138,13 @@ class EnergyAdjoint:
         B, nq = p.cfg.batch, 2 * p.cfg.n_modes
         grad = torch.zeros((B, max(nq, 1)), dtype=torch.float64, device=self.device)
         N = self.last_step
+        if not self.recompute:
+            p.adjoint_reset(self.obs_begin, self.obs_end)
+            p.adjoint_step_moments(self.all_records[:N + 1], grad, N + 1)
+            e1.record()
+            torch.cuda.synchronize()
+            self.timing["backward_ms"] = e0.elapsed_time(e1)
+            return grad[:, :nq].cpu().numpy()
         moments = self.records == "moments"
         rec = p.record_bytes if moments else p.state_bytes
         if self.ring is None or self.ring.shape != (self.C, rec):

@@ -1015,6 +1015,31 @@ int lbm_recompute(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *ri
     return LBM_OK;
 }
 
+int lbm_step_recording(lbm_ctx *c, int32_t n, void *records, size_t record_stride)
+{
+    CHECK_CTX(c);
+    if (n < 0 || (n > 0 && !records)) return fail(c, LBM_EINVAL, "lbm_step_recording: bad arguments");
+    if (c->cfg.pattern != 0 || c->fuse != 1)
+        return fail(c, LBM_EINVAL, "lbm_step_recording needs the two-buffer pattern and one step per launch");
+    if (c->cfg.collision != 0 || c->cfg.equilibrium != 0)
+        return fail(c, LBM_EINVAL, "lbm_step_recording: the paper's scheme only (collision = equilibrium = 0)");
+    if (record_stride < c->L.record_bytes || (record_stride & 255) || ((uintptr_t)records & 255))
+        return fail(c, LBM_EINVAL, "lbm_step_recording: record stride below the record size or not 256-byte aligned");
+    if (n == 0) return LBM_OK;
+    Tiles t = c->L.step;
+    t.b0 = 0;
+    t.nb = c->cfg.batch;
+    char *r = (char *)records;
+    for (int j = 0; j < n; ++j) {
+        const int bi = (int)((c->step + j + c->flip) & 1);
+        HIPCHK(c, launch_step_record(c->cfg.storage, c->geom, t, c->ws + c->L.off_state[bi],
+                                     c->ws + c->L.off_state[bi ^ 1], j, r + (size_t)j * record_stride, c->stream));
+    }
+    HIPCHK(c, launch_set_step(const_cast<long long *>(c->geom.step_dev), n, 1, c->stream));
+    c->step += n;
+    return LBM_OK;
+}
+
 int lbm_recompute_moments(lbm_ctx *c, const void *start, int64_t s0, int32_t n, void *scratch, size_t stride,
                           void *records, size_t record_stride)
 {

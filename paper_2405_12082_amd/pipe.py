@@ -85,6 +85,14 @@ class Pipe:
     def step(self, n: int = 1):
         self._check(self.lib.lbm_step(self._ctx, int(n)), "lbm_step")
 
+    def step_recording(self, records: torch.Tensor, n: int | None = None):
+        """n steps (default: one per record) recording the moments (rho - 1, j)
+        of each consumed state into ``records`` ([n][record_bytes] uint8)."""
+        n = records.shape[0] if n is None else n
+        stride = records.stride(0) * records.element_size()
+        self._check(self.lib.lbm_step_recording(self._ctx, int(n), C.c_void_p(_ptr(records)), C.c_size_t(stride)),
+                    "lbm_step_recording")
+
     def step_graph(self, n: int, k: int = 64):
         self._check(self.lib.lbm_step_graph(self._ctx, int(n), int(k)), "lbm_step_graph")
 

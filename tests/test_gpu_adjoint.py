@@ -230,3 +230,35 @@ def test_recompute_moments_rejects_bad_arguments(gpu):
     with pytest.raises(RuntimeError, match="two-buffer"):
         aa.recompute_moments(aa.save()[0], 0, scratch, rec)
     aa.close()
+
+
+@pytest.mark.parametrize("storage,wall,precision", [(0, 0, "fp32"), (0, 1, "fp32"), (1, 0, "fp32"), (2, 0, "fp64")])
+def test_recorded_forward_equals_checkpoint_and_recompute(gpu, storage, wall, precision):
+    """recompute=False (the forward run records the moments of every state;
+    the reverse sweep reads them in one call): J and the gradient equal
+    checkpoint-and-recompute's bitwise, since the recording step's states and
+    records are the forward's, and the sensitivities are summed per step
+    whatever the split of the sweep into calls."""
+    cfg = dict(TINY, wall=wall, storage=storage)
+    J1, g1 = gpu.EnergyAdjoint(cfg, 20, 40, checkpoint_every=7, precision=precision).gradient(TINY_AMPS[None])
+    J2, g2 = gpu.EnergyAdjoint(cfg, 20, 40, precision=precision, recompute=False).gradient(TINY_AMPS[None])
+    assert np.array_equal(J1, J2) and np.array_equal(g1, g2)
+
+
+def test_step_recording_rejects_bad_arguments(gpu):
+    import paper_2405_12082_amd as P
+    p = P.Pipe(TINY, TINY_AMPS[None])
+    rec = torch.empty((2, p.record_bytes), dtype=torch.uint8, device="cuda")
+    short = torch.empty((2, p.record_bytes - 256), dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError, match="lbm_step_recording"):
+        p.step_recording(short)
+    p.set_fused(2)
+    with pytest.raises(RuntimeError, match="one step per launch"):
+        p.step_recording(rec)
+    p.close()
+    aa = P.Pipe(dict(TINY, pattern=1), TINY_AMPS[None])
+    with pytest.raises(RuntimeError, match="two-buffer"):
+        aa.step_recording(rec)
+    aa.close()
+    with pytest.raises(ValueError):
+        gpu.EnergyAdjoint(TINY, 20, 40, records="states", recompute=False)

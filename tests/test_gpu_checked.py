@@ -125,7 +125,7 @@ def test_comparison_schemes(libs, kind, wall):
     _both(libs, cfg, run)
 
 
-@pytest.mark.parametrize("records", ["moments", "states"])
+@pytest.mark.parametrize("records", ["moments", "states", "recorded forward"])
 @pytest.mark.parametrize("storage", [0, 1])
 @pytest.mark.parametrize("wall", [0, 1])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -134,7 +134,10 @@ def test_adjoint_with_recompute(libs, wall, precision, storage, records):
     cfg = _cfg(wall=wall, nz=16, storage=storage)
     grads = []
     for lib in libs:
-        run = EnergyAdjoint(cfg, 20, 40, checkpoint_every=10, precision=precision, library=lib, records=records)
+        if records == "recorded forward":
+            run = EnergyAdjoint(cfg, 20, 40, precision=precision, library=lib, recompute=False)
+        else:
+            run = EnergyAdjoint(cfg, 20, 40, checkpoint_every=10, precision=precision, library=lib, records=records)
         J, g = run.gradient(_amps(cfg))
         flags, checked = run.pipe.check_flags()
         assert flags == 0, f"bounds-check flags {flags:#x}"
