@@ -162,6 +162,7 @@ int main(void)
     if (lbm_ring_spectrum_static(NULL, 1, 1, 64, 4, NULL, NULL, NULL, NULL) != LBM_EINVAL) return 17;
     if (lbm_recompute_moments(NULL, NULL, 0, 1, NULL, 0, NULL, 0) != LBM_EINVAL) return 19;
     if (lbm_adjoint_step_moments(NULL, 1, NULL, 0, NULL) != LBM_EINVAL) return 20;
+    if (lbm_step_recording(NULL, 1, NULL, 0) != LBM_EINVAL) return 22;
     lbm_config r = base();
     r.adjoint = 1;
     lbm_layout rl;
