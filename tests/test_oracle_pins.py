@@ -19,8 +19,10 @@ def O(oracle_mod):
     return oracle_mod
 
 
-@pytest.fixture(scope="module")
+@pytest.fixture
 def rng():
+    """A fresh seeded generator per test: each test's random inputs are the
+    same whatever ran before it (also across parallel workers)."""
     return np.random.default_rng(20240520)
 
 
@@ -328,9 +330,12 @@ def test_mass_conserved_with_bounce_back_not_with_bouzidi(O):
     assert drift[1][0] > 1e-10 and drift[1][1] > 5 * drift[1][0]
 
 
-def test_periodic_box_momentum_grows_by_force_times_mass(O, rng):
+def test_periodic_box_momentum_grows_by_force_times_mass(O):
     """No wall: total mass is constant and total momentum grows by a * M per
-    step, exactly (collision adds rho a at each node, streaming permutes)."""
+    step, exactly (collision adds rho a at each node, streaming permutes).
+    In FP64 the dense transforms of 20 steps at 210 nodes round each
+    population to ~1e-16 relative, so the sums hold to 1e-13 of the mass."""
+    rng = np.random.default_rng(20240521)  # this test's own input, whatever ran before
     cfg = O.make_config(nx=6, ny=5, nz=7, radius=0.0, tau=0.9, accel_z=3e-5)
     p = O.Pipe(cfg)
     f = p.get_f() * (1.0 + rng.uniform(-0.01, 0.01, size=p.get_f().shape))
@@ -338,9 +343,10 @@ def test_periodic_box_momentum_grows_by_force_times_mass(O, rng):
     s0 = p.sums()
     p.step(20)
     s1 = p.sums()
-    assert abs(s1[0] - s0[0]) < 1e-12
-    np.testing.assert_allclose(s1[1:3], s0[1:3], atol=1e-12)
-    assert abs(s1[3] - (s0[3] + 20 * 3e-5 * s0[0])) < 1e-12
+    tol = 1e-13 * s0[0]
+    assert abs(s1[0] - s0[0]) < tol
+    np.testing.assert_allclose(s1[1:3], s0[1:3], atol=tol)
+    assert abs(s1[3] - (s0[3] + 20 * 3e-5 * s0[0])) < tol
 
 
 # ------------------------------------------------------------------ trigger force
