@@ -365,16 +365,18 @@ int lbm_recompute(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *
  * cursor as lbm_adjoint_step.  Async. */
 int lbm_recompute_moments(lbm_ctx *ctx, const void *start, int64_t s0, int32_t n, void *scratch, size_t stride,
                           void *records, size_t record_stride);
+int lbm_adjoint_step_moments(lbm_ctx *ctx, int32_t n, const void *records, size_t record_stride, double *grad);
+
 /* n steps of the context's own state, as lbm_step does them, step j
  * recording the moments of the state it consumes (the state of step
  * c + j, c the step index before the call) into records[j] (layout and
  * stride as lbm_recompute_moments).  With the records of every step of a
  * forward run kept in device memory (record_bytes each: 39 MB for a
- * 96x96x384 pipe, 78 GB for 2000 steps of it) the reverse sweep needs no
- * recompute.  Two-buffer pattern, one step per launch and the paper's scheme
- * only (LBM_EINVAL otherwise).  Async. */
+ * 96x96x384 pipe, 78 GB for 2000 steps of it) the reverse sweep
+ * (lbm_adjoint_step_moments over them) needs no recompute.  Two-buffer
+ * pattern, one step per launch and the paper's scheme only (LBM_EINVAL
+ * otherwise).  Async. */
 int lbm_step_recording(lbm_ctx *ctx, int32_t n, void *records, size_t record_stride);
-int lbm_adjoint_step_moments(lbm_ctx *ctx, int32_t n, const void *records, size_t record_stride, double *grad);
 
 /* Measurement aid: enqueue n copies of the current state buffer into the
  * other buffer with the launch geometry of lbm_step (27 aligned loads and 27
