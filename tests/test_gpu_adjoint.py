@@ -262,3 +262,41 @@ def test_step_recording_rejects_bad_arguments(gpu):
     aa.close()
     with pytest.raises(ValueError):
         gpu.EnergyAdjoint(TINY, 20, 40, records="states", recompute=False)
+
+
+@pytest.mark.parametrize("storage,wall", [(0, 0), (0, 1), (1, 0), (2, 0)])
+def test_recorded_moments_match_the_oracle_per_node(gpu, oracle_mod, storage, wall):
+    """Each recorded moment, node by node, against the FP64 oracle's moments
+    of the same state (the exported populations f^n): rho - 1, and j from
+    the oracle's u = j/rho + a(x, n)/2 and its force at that step.  Bound per
+    node: 27 roundings of the largest population, 27 * 2^-24 * sum_i |g_i|
+    (the FP32 sum, or the FP32 export the oracle starts from)."""
+    import paper_2405_12082_amd as P
+    O = oracle_mod
+    cfg = dict(TINY, storage=storage, wall=wall)
+    p = P.Pipe(cfg, TINY_AMPS[None])
+    p.step(6)
+    start, s0 = p.save()
+    g = p.populations()[0].cpu().numpy().astype(np.float64)  # [27][nz][ny][nx]
+    scratch = torch.empty((2, p.state_bytes), dtype=torch.uint8, device="cuda")
+    rec = torch.empty((1, p.record_bytes), dtype=torch.uint8, device="cuda")
+    p.recompute_moments(start, s0, scratch, rec)
+    lay = p.layout
+    ncol, pitch, ps, nz = int(lay.n_fluid_columns), int(lay.plane_pitch), int(lay.population_stride), cfg["nz"]
+    dt = np.float64 if storage == 2 else np.float32
+    r = rec[0].cpu().numpy().view(dt)[:4 * ps].reshape(4, ps)[:, :nz * pitch].reshape(4, nz, pitch)[:, :, :ncol]
+    p.close()
+    o = O.Pipe(O.make_config(**cfg), TINY_AMPS)
+    mask = o.fluid_mask()
+    ys, xs = np.nonzero(mask[0])  # the fluid columns in row-major order
+    assert ys.size == ncol
+    _, w, _ = O.lattice()
+    o.set_f(g + w[:, None, None, None], s0)
+    rho, u = o.moments()
+    a = o.force(s0)
+    ref = np.stack([rho - 1.0] + [rho * (u[q] - 0.5 * a[q]) for q in range(3)])[:, :, ys, xs]
+    bound = 27 * 2.0 ** -24 * np.abs(g).sum(axis=0)[:, ys, xs]
+    err = np.abs(r.astype(np.float64) - ref)
+    _log(f"storage {storage} wall {wall}: records vs oracle moments, worst ratio to the bound "
+         f"{(err / bound[None]).max():.3f}")
+    assert np.all(err <= bound[None])
